@@ -1,0 +1,106 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module holds no SNAP arithmetic: it only draws positions and
+coefficients.  The paper measures on a tungsten SNAP input (2000 atoms, 26
+neighbours per atom, Sec. II.C and Table I) whose trained coefficients are
+not available; a body-centred-cubic lattice with the same shape stands in for
+it: lattice constant 3.1803 A, so the first three shells (8 at 2.754 A, 6 at
+3.180 A, 12 at 4.498 A) give 26 neighbours inside rcut = 4.73 A, the next
+shell sits at 5.274 A.  Coefficients are drawn from N(0, 0.1^2) (0.1 is the
+standard deviation).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+A_BCC = 3.1803
+RCUT = 4.73
+RFAC0 = 0.99363
+RMIN0 = 0.0
+
+
+def bcc(ncell: int, sigma: float, seed: int, a: float = A_BCC):
+    """BCC crystal of ncell^3 cubic cells with Gaussian displacements.
+
+    Atom order is cell-major: index = ((ix*n + iy)*n + iz)*2 + basis.
+    Returns (pos [N,3] float64 wrapped into [0, L), box [3]).
+    """
+    rng = np.random.default_rng(seed)
+    idx = np.arange(ncell)
+    ix, iy, iz = np.meshgrid(idx, idx, idx, indexing="ij")
+    corner = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])
+    sites = (corner[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    L = ncell * a
+    pos = sites + rng.normal(0.0, sigma, size=sites.shape)
+    pos = np.mod(pos, L)
+    return np.ascontiguousarray(pos), np.array([L, L, L])
+
+
+def bcc_with_vacancies(ncell: int, nvac: int, sigma: float, vac_seed: int, pos_seed: int,
+                       a: float = A_BCC):
+    """BCC crystal with nvac sites removed at random, then displaced."""
+    sites, box = bcc(ncell, 0.0, 0, a)
+    rng_v = np.random.default_rng(vac_seed)
+    drop = rng_v.choice(len(sites), size=nvac, replace=False)
+    keep = np.setdiff1d(np.arange(len(sites)), drop)
+    sites = sites[keep]
+    rng = np.random.default_rng(pos_seed)
+    pos = np.mod(sites + rng.normal(0.0, sigma, size=sites.shape), box[0])
+    return np.ascontiguousarray(pos), box
+
+
+def cluster(natoms: int, radius: float, seed: int, min_dist: float = 1.8):
+    """Random isolated cluster inside a sphere (non-periodic box)."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < natoms:
+        p = rng.uniform(-radius, radius, size=3)
+        if np.linalg.norm(p) > radius:
+            continue
+        if all(np.linalg.norm(p - q) >= min_dist for q in pts):
+            pts.append(p)
+    return np.ascontiguousarray(np.array(pts)), np.array([0.0, 0.0, 0.0])
+
+
+def beta(ncoeff: int, seed: int, sd: float = 0.1, natoms: int | None = None):
+    """Linear coefficients ~ N(0, sd^2): shape [ncoeff] or [natoms, ncoeff]."""
+    rng = np.random.default_rng(seed)
+    shape = (ncoeff,) if natoms is None else (natoms, ncoeff)
+    return rng.normal(0.0, sd, size=shape)
+
+
+def ncoeff(twojmax: int) -> int:
+    """Number of bispectrum components for a given twojmax (counting only)."""
+    n = 0
+    for j1 in range(twojmax + 1):
+        for j2 in range(j1 + 1):
+            for j in range(j1 - j2, min(twojmax, j1 + j2) + 1, 2):
+                if j >= j1:
+                    n += 1
+    return n
+
+
+# Named workloads (sizes of the paper's benchmark and its variations).
+WORKLOADS = {
+    # 128 atoms, 2J=4: small parity case
+    "bcc128_2j4": dict(ncell=4, sigma=0.05, pos_seed=1, beta_seed=2, twojmax=4),
+    # 2000 atoms, 26 neighbours, 2J=8: the paper's benchmark shape
+    "bcc2000_2j8": dict(ncell=10, sigma=0.05, pos_seed=3, beta_seed=4, twojmax=8),
+    # same positions, 2J=14 (204 components)
+    "bcc2000_2j14": dict(ncell=10, sigma=0.05, pos_seed=3, beta_seed=5, twojmax=14),
+    # 16000 sites, 800 vacancies, sigma 0.15: uneven 16-30 neighbours
+    "bcc15200vac_2j8": dict(ncell=20, nvac=800, sigma=0.15, vac_seed=6, pos_seed=7, beta_seed=4,
+                            twojmax=8),
+}
+
+
+def make(name: str):
+    """Return (pos, box, beta, twojmax) for a named workload."""
+    w = WORKLOADS[name]
+    if "nvac" in w:
+        pos, box = bcc_with_vacancies(w["ncell"], w["nvac"], w["sigma"], w["vac_seed"], w["pos_seed"])
+    else:
+        pos, box = bcc(w["ncell"], w["sigma"], w["pos_seed"])
+    b = beta(ncoeff(w["twojmax"]), w["beta_seed"])
+    return pos, box, b, w["twojmax"]
