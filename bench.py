@@ -1,0 +1,215 @@
+"""Benchmark: SNAP energy + force throughput (atom-steps/s) on one MI355X.
+
+One step is one full evaluation of the hot path on a fixed synthetic input
+already resident in device memory: compute_U -> compute_Y -> compute_dE ->
+update_forces (four kernels, one snap_compute call).  The neighbour list is
+built once on the host, as in molecular dynamics where it persists across
+steps.
+
+Prints one JSON line (see the bench contract in the design doc): throughput, the
+roofline of the dominant kernel (algorithmic FP64 flops per launch divided by
+its average duration, measured with HIP events on the launch stream), and the
+CPU oracle timed on this host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+
+
+# --------------------------------------------------------------------------
+# algorithmic work (FP64 flops; an FMA counts 2), per unit of each stage
+# --------------------------------------------------------------------------
+def _element_costs(twojmax):
+    """Per-pair recursion flops of the stored half, in the kernels' order:
+    column q, level J = (q ? 2q : 0)..twojmax, rows p = 0..J.  Row p of level
+    J costs 14 flops for u (two conj-products and a difference), 6 at the
+    ends of the column (one product); each derivative direction costs 30 (14
+    at the ends); contracting with Y costs 4 per quantity."""
+    u = du = 0
+    nel = 0
+    for q in range(twojmax // 2 + 1):
+        for J in range(2 * q if q else 0, twojmax + 1):
+            for p in range(J + 1):
+                nel += 1
+                if J == 0:
+                    continue
+                interior = 0 < p < J
+                u += 14 if interior else 6
+                du += 30 if interior else 14
+    return nel, u, du
+
+
+def algorithmic_flops(twojmax, natoms, npairs, nterms, nitems):
+    nel, u_rec, du_rec = _element_costs(twojmax)
+    flops = {
+        # recursion + f_c weighting (2/element) + per-atom sum (2/element)
+        "compute_U": npairs * (u_rec + 4 * nel),
+        # 10 per Clebsch-Gordan term (complex product, real weight, accumulate)
+        # and 6 per Z element (coefficient times Z into Y)
+        "compute_Y": natoms * (10 * nterms + 6 * nitems),
+        # u once, du for three directions, four dot products with Y, and
+        # dE = f_c' n S0 + f_c S per direction
+        "compute_dE": npairs * (u_rec + 3 * du_rec + 16 * nel + 9),
+        # 6 per pair (gather) and 4 per element (energy)
+        "update_forces": 6 * npairs + 4 * nel * natoms,
+    }
+    return flops
+
+
+def algorithmic_bytes(twojmax, natoms, npairs, nhalf):
+    """Minimum HBM traffic per launch (bytes) if every input is read once."""
+    return {
+        "compute_U": natoms * 24 + (natoms + 1) * 4 + npairs * 4 + natoms * nhalf * 16 + npairs * 4,
+        "compute_Y": 2 * natoms * nhalf * 16,
+        "compute_dE": natoms * nhalf * 16 + natoms * 24 + npairs * (4 + 4 + 24),
+        "update_forces": natoms * 4 + npairs * (4 + 48) + 2 * natoms * nhalf * 16 + natoms * 32,
+    }
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("snap_kernels.hip", "snap_tables.cpp", "snap_abi.cpp"):
+        with open(os.path.join(ROOT, "paper_2011_12875_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    v = d.get("kernels", {}).get(kernel)
+    return None if v is None else float(v.get("bytes_per_launch"))
+
+
+def cpu_baseline(pos, box, beta, twojmax, budget_s=12.0):
+    """The oracle (plain FP64 C, OpenMP over central atoms, literal dB/dr
+    forces) on this host, repeated on the full workload until about budget_s
+    seconds of work; atom-steps/s = atoms evaluated / wall time."""
+    import oracle
+    from paper_2011_12875_amd import workloads as wl
+    oracle.build()
+    threads = oracle.max_threads()
+    n = len(pos)
+    done = 0
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.snap(pos, box, twojmax, wl.RCUT, wl.RFAC0, wl.RMIN0, 1, beta=beta, want_dE=False)
+        reps += 1
+        done += n
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d full evaluations of the same %d-atom workload (E+F, %.1f s; includes "
+                      "the oracle's O(N^2) neighbour search)" % (reps, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="bcc2000_2j8")
+    ap.add_argument("--dedr-dirs", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2011_12875_amd import snapmi
+    from paper_2011_12875_amd import workloads as wl
+
+    pos, box, beta, tj = wl.make(args.workload)
+    n = len(pos)
+    pot = snapmi.SnapPotential(tj, wl.RCUT, wl.RFAC0, wl.RMIN0, 1, dedr_dirs=args.dedr_dirs)
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    tpos = torch.as_tensor(pos, device="cuda")
+    tbeta = torch.as_tensor(beta, device="cuda")
+    out = {"energy": torch.empty(n, dtype=torch.float64, device="cuda"),
+           "force": torch.empty((n, 3), dtype=torch.float64, device="cuda")}
+
+    for _ in range(args.warmup):
+        pot.compute(tpos, box, nl, tbeta, out=out)
+    pot.sync_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pot.compute(tpos, box, nl, tbeta, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step * 1e-3)
+    pot.sync_status()
+
+    # per-stage durations: HIP events recorded by the library around each
+    # stage, on the stream the kernels run on, over a second timed pass
+    pot.profile(True)
+    for _ in range(args.steps):
+        pot.compute(tpos, box, nl, tbeta, out=out)
+    stages = pot.stage_times()
+    pot.profile(False)
+    avg_ms = {k: v[0] / v[1] for k, v in stages.items() if v[1] > 0}
+
+    nterms, nitems, _ = pot.program_size()
+    flops = algorithmic_flops(tj, n, nl.npairs, nterms, nitems)
+    hbm = algorithmic_bytes(tj, n, nl.npairs, pot.nhalf)
+    dominant = max(("compute_U", "compute_Y", "compute_dE"), key=lambda k: avg_ms.get(k, 0.0))
+    achieved = flops[dominant] / (avg_ms[dominant] * 1e-3) / 1e12
+    traffic = read_traffic(args.workload, dominant)
+
+    res = {
+        "metric": "atom-steps/s SNAP E+F at 2J=8, 2000 atoms",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "atoms": n, "pairs": nl.npairs, "twojmax": tj,
+                   "ncoeff": pot.ncoeff, "rcut": wl.RCUT, "rfac0": wl.RFAC0,
+                   "lattice": "bcc a=3.1803 A", "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic},
+        "stages_ms": {k: round(v, 5) for k, v in avg_ms.items()},
+        "stage_tflops": {k: flops[k] / (avg_ms[k] * 1e-3) / 1e12 for k in flops if k in avg_ms},
+        "stage_algorithmic_gbs": {k: hbm[k] / (avg_ms[k] * 1e-3) / 1e9 for k in hbm
+                                  if k in avg_ms},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(pos, box, beta, tj)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * snapmi.h -- C ABI of the MI355X (gfx950) SNAP energy-and-force library.
+ *
+ * The library evaluates the SNAP potential of Gayatri et al., "Rapid
+ * Exploration of Optimization Strategies on Advanced Architectures using
+ * TestSNAP and LAMMPS" (arXiv 2011.12875), in FP64, with the adjoint
+ * formulation of its Sec. IV:
+ *   compute_U  -- eq. (u): per-pair hyperspherical harmonics by the
+ *                 recursion of eq. (hysphrecur), summed per atom (Sec. VI);
+ *   compute_Y  -- eq. (y): Clebsch-Gordan products of eq. (z) weighted by
+ *                 the linear coefficients and accumulated into Y_j;
+ *   compute_dE -- eq. (snapforce2): per-pair dE = Y : dU^* (Sec. VI,
+ *                 "compute_fused_dE"), kept per pair as in Sec. IV;
+ *   update_forces -- the per-pair derivatives scattered to atoms.
+ * The energy E_i of eq. (snapatomenergy) is returned per atom.
+ *
+ * Conventions used throughout:
+ *   - units: positions and lengths in Angstrom; beta and energies in eV;
+ *     forces and pair derivatives in eV/Angstrom;
+ *   - twojmax is 2J of the paper (twice the maximum angular momentum);
+ *     N_B (snap_ncoeff) bispectrum components are ordered J1 ascending,
+ *     J2 = 0..J1, then J ascending, with J2 <= J1 <= J, the triangle rule
+ *     and J1+J2+J even (the enumeration of Sec. II.A);
+ *   - the neighbour list is a FULL list in CSR form: the pairs of atom i are
+ *     p = off[i] .. off[i+1]-1, pair p = (i -> nbr[p]), and rev[p] is the
+ *     index of the reverse pair (nbr[p] -> i).  Pairs with r >= rcut are
+ *     allowed (a skin) and contribute nothing; i must not appear in its own
+ *     list.  Orthorhombic box; box[d] <= 0 means dimension d is not
+ *     periodic; a periodic edge must be at least 2*rcut (minimum image);
+ *   - "dev" pointers are HIP device pointers, "host" pointers are ordinary
+ *     host memory.  The caller owns every buffer it passes; the library owns
+ *     its context (tables and workspace) until snap_destroy;
+ *   - every call returns SNAP_OK (0) or a negative error code and never
+ *     aborts; snap_last_error() gives a message for the last failure of the
+ *     calling thread.
+ */
+#ifndef SNAPMI_H
+#define SNAPMI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNAP_OK 0
+#define SNAP_EINVAL (-1) /* an argument is out of range                        */
+#define SNAP_EBOX (-2)   /* periodic box edge shorter than 2*rcut              */
+#define SNAP_ENBR (-3)   /* neighbour list inconsistent (index, self, reverse) */
+#define SNAP_EGEOM (-4)  /* coincident atoms (r < 1e-10 A) or non-finite data  */
+#define SNAP_ENOMEM (-5) /* device or host allocation failed                   */
+#define SNAP_EDEV (-6)   /* HIP runtime error or no usable gfx950 device       */
+
+#define SNAP_MAX_TWOJMAX 14
+
+typedef struct snap_ctx snap_ctx;
+
+/* Parameters of the potential (Sec. II.A; the 3-sphere map, switching
+ * function and self-contribution that the paper omits are fixed here):
+ *   theta0 = rfac0 * pi * (r - rmin0) / (rcut - rmin0);
+ *   f_c(r) = (cos(pi (r - rmin0)/(rcut - rmin0)) + 1)/2 for rmin0 < r < rcut,
+ *            1 for r <= rmin0, and 1 everywhere if switch_flag == 0;
+ *   U_j    = wself * identity + sum over neighbours of f_c u_j.           */
+typedef struct {
+    int twojmax;       /* 0 .. SNAP_MAX_TWOJMAX                               */
+    double rcut;       /* > 0                                                 */
+    double rfac0;      /* (0, 1]                                              */
+    double rmin0;      /* [0, rcut)                                           */
+    int switch_flag;   /* 0 or 1                                              */
+    double wself;      /* self weight on the diagonal of every U_j (1.0)     */
+    int dedr_dirs;     /* directions per lane in compute_dE: 1 or 3 (0: auto) */
+} snap_params;
+
+/* Create a context for one parameter set.  Builds the host index tables
+ * (half-matrix layout of Sec. VI, Clebsch-Gordan coefficients, the Y
+ * contraction program); device tables are uploaded on first use.  wself = 1,
+ * dedr_dirs = auto.  *out receives the context (owned by the library).
+ * Errors: SNAP_EINVAL for out-of-range parameters, SNAP_ENOMEM. */
+int snap_setup(int twojmax, double rcut, double rfac0, double rmin0, int switch_flag,
+               snap_ctx **out);
+
+/* As snap_setup with every field of snap_params. */
+int snap_setup_ex(const snap_params *p, snap_ctx **out);
+
+/* Release the context, its tables and its device workspace. NULL is a no-op. */
+int snap_destroy(snap_ctx *c);
+
+/* Number of bispectrum components N_B (14, 55, 204 for 2J = 4, 8, 14;
+ * Sec. II.C).  Returns a negative code for a NULL context. */
+int snap_ncoeff(const snap_ctx *c);
+
+/* Number of stored (half-matrix) elements of U_j and Y_j over all j: the
+ * elements (J, p, q) with q <= J/2 (Sec. VI, symmetry halving). */
+int snap_nhalf(const snap_ctx *c);
+
+/* Host copy of a table, for inspection and tests.  which:
+ *   0: components, int[3*N_B] (J1, J2, J)
+ *   1: half elements, int[3*nhalf] (J, p, q) in storage order
+ *   2: Clebsch-Gordan values used on the device, double, one per
+ *      (J1, J2, J, M1, M2) in the order of snap_table(3)
+ *   3: the keys of table 2, int[5 * count]
+ *   4: sizes of the contraction program, int[3]: Clebsch-Gordan terms, Z
+ *      items and Y rows (the work of compute_Y per atom)
+ * buf has room for cap elements of the table's type; returns the number of
+ * elements of the table (which may exceed cap: nothing beyond cap is
+ * written), or SNAP_EINVAL. */
+int snap_table(const snap_ctx *c, int which, void *buf, int cap);
+
+/* Build a full neighbour list on the host with a cell list (r < rcut).
+ *   pos_host[n][3], box[3] as above;
+ *   off[n+1], nbr[cap], rev[cap] receive the CSR list (host memory);
+ *   *npairs receives the pair count.  Within each atom the neighbours are
+ *   sorted by index.  Returns SNAP_OK, SNAP_ENOMEM if cap is too small
+ *   (*npairs then holds the required size), SNAP_EBOX, SNAP_EINVAL. */
+int snap_build_neighbors(const double *pos_host, int n, const double box[3], double rcut, int *off,
+                         int *nbr, int *rev, int cap, int *npairs);
+
+/* Check a host neighbour list: indices in range, no self pairs, off
+ * non-decreasing with off[0] = 0 and off[n] = npairs, and rev consistent
+ * (rev[rev[p]] == p and the reverse pair joins the same two atoms).
+ * Returns SNAP_OK or SNAP_ENBR. */
+int snap_check_neighbors(int n, const int *off, const int *nbr, const int *rev, int npairs);
+
+/* SNAP energies and forces (the stage sequence of Sec. IV, Listing 5).
+ *   n, npairs       atom and pair counts (host ints; npairs == off[n]);
+ *   pos   dev  double[n][3]
+ *   box   host double[3]
+ *   off   dev  int[n+1], nbr dev int[npairs], rev dev int[npairs]
+ *   beta  dev  double[N_B] (per_atom_beta == 0) or double[n][N_B]
+ *   energy dev double[n]        E_i (eq. snapatomenergy)
+ *   force  dev double[n][3]     F_i = -dE/dr_i
+ *   bispec dev double[n][N_B] or NULL: the bispectrum B_i (eq. z)
+ *   dE_pair dev double[npairs][3] or NULL: dE_i/dr_ik of pair (i -> k)
+ *   stream  hipStream_t (NULL = default stream)
+ * Work is enqueued on the stream and the call returns without waiting.
+ * Coincident atoms are detected on the device and reported by the next
+ * snap_sync_status.  Errors: SNAP_EINVAL, SNAP_EBOX, SNAP_ENOMEM, SNAP_EDEV. */
+int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                 const int *off, const int *nbr, const int *rev, const double *beta,
+                 int per_atom_beta, double *energy, double *force, double *bispec,
+                 double *dE_pair, void *stream);
+
+/* The forward half used by automatic differentiation: compute_U and the
+ * bispectrum only.  energy = sum_l beta_l B_l per atom.  Same arguments as
+ * snap_compute; the context keeps U_j of this call for snap_backward. */
+int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                 const int *off, const int *nbr, const int *rev, const double *beta,
+                 int per_atom_beta, double *energy, double *bispec, void *stream);
+
+/* The reverse sweep (Sec. IV: the adjoint Y is reverse-mode differentiation
+ * of B with respect to U): given g_i = dL/dE_i (dev double[n]), computes
+ * force = -dL/dr (dev double[n][3]) with Y built from the per-atom
+ * coefficients g_i * beta, using the U_j kept by the last snap_forward on the
+ * same context and stream.  dE_pair as in snap_compute (may be NULL). */
+int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                  const int *off, const int *nbr, const int *rev, const double *beta,
+                  int per_atom_beta, const double *grad_energy, double *force, double *dE_pair,
+                  void *stream);
+
+/* Copy an internal per-atom array of the last call into dst (dev memory):
+ * which = 0: U_j, which = 1: Y_j.  Layout: double[nhalf][n][2] (element-
+ * major, re/im interleaved), elements in the order of snap_table(1). */
+int snap_copy_workspace(snap_ctx *c, int which, double *dst, void *stream);
+
+/* Stage timing with HIP events recorded on the call's stream, around each
+ * stage of every later snap_compute / snap_forward / snap_backward while
+ * enabled (enable = 1), off again with enable = 0 (the default).  Stages:
+ * 0 compute_U, 1 compute_Y, 2 compute_dE, 3 update_forces (+ energy),
+ * 4 bispectrum.  Recording adds one event per stage boundary; the kernels
+ * themselves are unchanged. */
+int snap_profile(snap_ctx *c, int enable);
+
+/* Wait for the recorded events and return, per stage, the summed elapsed
+ * milliseconds (ms[5], host) and the number of launches (launches[5], host)
+ * since the last call; then clear the record. */
+int snap_stage_times(snap_ctx *c, double ms[5], int launches[5]);
+
+/* Wait for the stream and report a device-side error of the previous calls
+ * (SNAP_EGEOM for coincident atoms), clearing it.  SNAP_OK otherwise. */
+int snap_sync_status(snap_ctx *c, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *snap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAPMI_H */

@@ -1,0 +1,550 @@
+// snap_abi.cpp -- the C ABI of snapmi.h: contexts, device tables, workspace,
+// argument checks and the launch sequence of one evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/snapmi.h"
+#include "snap_kernels.hpp"
+#include "snap_tables.hpp"
+
+using namespace snapmi;
+
+struct snap_ctx {
+    snap_params prm;
+    Tables tab;
+    DevTables dev;
+    bool dev_ready = false;
+    int device = -1;
+    Work work;
+    int cap_atoms = 0;   // npad the per-atom workspace holds
+    int cap_pairs = 0;   // pairs the dE / pair_atom workspace holds
+    int last_n = 0;
+    // stage timing (snap_profile): event pairs recorded per stage
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+};
+
+static hipEvent_t take_event(snap_ctx *c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records the start of a stage on the stream when profiling; finish() the end.
+struct StageTimer {
+    snap_ctx *c;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageTimer(snap_ctx *c_, int stage_, hipStream_t s_) : c(c_), stage(stage_), s(s_)
+    {
+        if (c->profiling && (a = take_event(c))) (void)hipEventRecord(a, s);
+    }
+    void finish()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        c->ev_used.push_back({stage, {a, b}});
+        a = nullptr;
+    }
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? SNAP_ENOMEM : SNAP_EDEV, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+template <class T>
+static hipError_t upload(T *&dst, const std::vector<T> &src)
+{
+    const size_t bytes = sizeof(T) * (src.empty() ? 1 : src.size());
+    hipError_t e = hipMalloc((void **)&dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+static void free_dev(snap_ctx *c)
+{
+    DevTables &d = c->dev;
+    (void)hipFree(d.unscale_u);
+    (void)hipFree(d.unscale_y);
+    (void)hipFree(d.terms);
+    (void)hipFree(d.items);
+    (void)hipFree(d.rows);
+    (void)hipFree(d.bitems);
+    (void)hipFree(d.bl_begin);
+    d = DevTables();
+    Work &w = c->work;
+    (void)hipFree(w.U);
+    (void)hipFree(w.Y);
+    (void)hipFree(w.dE);
+    (void)hipFree(w.pair_atom);
+    (void)hipFree(w.flag);
+    w = Work();
+    c->dev_ready = false;
+    c->cap_atoms = c->cap_pairs = 0;
+}
+
+static int ensure_device(snap_ctx *c)
+{
+    if (c->dev_ready) return SNAP_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SNAP_EDEV, "device %d is %s; this library is built for gfx950", dev,
+                    prop.gcnArchName);
+    const Tables &t = c->tab;
+    DevTables &d = c->dev;
+    HIP_TRY(upload(d.unscale_u, t.unscale_u), "upload unscale_u");
+    HIP_TRY(upload(d.unscale_y, t.unscale_y), "upload unscale_y");
+    HIP_TRY(upload(d.terms, t.terms), "upload terms");
+    HIP_TRY(upload(d.items, t.items), "upload items");
+    HIP_TRY(upload(d.rows, t.rows), "upload rows");
+    HIP_TRY(upload(d.bitems, t.bitems), "upload bitems");
+    HIP_TRY(upload(d.bl_begin, t.bl_begin), "upload bl_begin");
+    d.nrows = (int)t.rows.size();
+    HIP_TRY(hipMalloc((void **)&c->work.flag, sizeof(int)), "alloc flag");
+    HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
+    c->device = dev;
+    c->dev_ready = true;
+    return SNAP_OK;
+}
+
+// Grow the workspace to n atoms and np pairs.  Growing waits for the stream
+// (the old buffers may still be in use) and clears the new per-atom arrays so
+// that padding lanes always read finite values.
+static int ensure_work(snap_ctx *c, int n, int np, hipStream_t s)
+{
+    const int npad = ((n + 63) / 64) * 64;
+    Work &w = c->work;
+    const size_t nh = (size_t)c->tab.nhalf;
+    if (npad > c->cap_atoms) {
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        (void)hipFree(w.U);
+        (void)hipFree(w.Y);
+        w.U = w.Y = nullptr;
+        c->cap_atoms = 0;
+        HIP_TRY(hipMalloc((void **)&w.U, sizeof(double2) * nh * npad), "alloc U");
+        HIP_TRY(hipMalloc((void **)&w.Y, sizeof(double2) * nh * npad), "alloc Y");
+        HIP_TRY(hipMemset(w.U, 0, sizeof(double2) * nh * npad), "clear U");
+        HIP_TRY(hipMemset(w.Y, 0, sizeof(double2) * nh * npad), "clear Y");
+        c->cap_atoms = npad;
+    }
+    if (np > c->cap_pairs) {
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        (void)hipFree(w.dE);
+        (void)hipFree(w.pair_atom);
+        w.dE = nullptr;
+        w.pair_atom = nullptr;
+        c->cap_pairs = 0;
+        HIP_TRY(hipMalloc((void **)&w.dE, sizeof(double) * 3 * (size_t)np), "alloc dE");
+        HIP_TRY(hipMalloc((void **)&w.pair_atom, sizeof(int) * (size_t)np), "alloc pair_atom");
+        c->cap_pairs = np;
+    }
+    // element-major arrays use the capacity as their stride
+    w.npad = c->cap_atoms;
+    return SNAP_OK;
+}
+
+static int check_params(const snap_params *p)
+{
+    if (!p) return fail(SNAP_EINVAL, "NULL parameters");
+    if (p->twojmax < 0 || p->twojmax > SNAP_MAX_TWOJMAX)
+        return fail(SNAP_EINVAL, "twojmax %d outside 0..%d", p->twojmax, SNAP_MAX_TWOJMAX);
+    if (!(p->rcut > 0.0) || !std::isfinite(p->rcut)) return fail(SNAP_EINVAL, "rcut must be > 0");
+    if (!(p->rfac0 > 0.0 && p->rfac0 <= 1.0)) return fail(SNAP_EINVAL, "rfac0 must be in (0, 1]");
+    if (!(p->rmin0 >= 0.0 && p->rmin0 < p->rcut))
+        return fail(SNAP_EINVAL, "rmin0 must be in [0, rcut)");
+    if (p->switch_flag != 0 && p->switch_flag != 1)
+        return fail(SNAP_EINVAL, "switch_flag must be 0 or 1");
+    if (!std::isfinite(p->wself)) return fail(SNAP_EINVAL, "wself must be finite");
+    if (p->dedr_dirs != 0 && p->dedr_dirs != 1 && p->dedr_dirs != 3)
+        return fail(SNAP_EINVAL, "dedr_dirs must be 0, 1 or 3");
+    return SNAP_OK;
+}
+
+static int check_box(const double box[3], double rcut)
+{
+    if (!box) return fail(SNAP_EINVAL, "NULL box");
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(box[d])) return fail(SNAP_EINVAL, "box[%d] is not finite", d);
+        if (box[d] > 0.0 && box[d] < 2.0 * rcut)
+            return fail(SNAP_EBOX, "periodic box edge %d (%g) shorter than 2*rcut (%g)", d, box[d],
+                        2.0 * rcut);
+    }
+    return SNAP_OK;
+}
+
+static Geom make_geom(const snap_ctx *c, const double box[3])
+{
+    Geom g;
+    g.rcut = c->prm.rcut;
+    g.rfac0 = c->prm.rfac0;
+    g.rmin0 = c->prm.rmin0;
+    g.wself = c->prm.wself;
+    g.switch_flag = c->prm.switch_flag;
+    for (int d = 0; d < 3; ++d) g.box[d] = box[d] > 0.0 ? box[d] : 0.0;
+    return g;
+}
+
+static int dedr_dirs(const snap_ctx *c)
+{
+    if (c->prm.dedr_dirs) return c->prm.dedr_dirs;
+    return 1;
+}
+
+extern "C" {
+
+const char *snap_last_error(void) { return g_err.c_str(); }
+
+int snap_setup_ex(const snap_params *p, snap_ctx **out)
+{
+    if (!out) return fail(SNAP_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    int st = check_params(p);
+    if (st) return st;
+    snap_ctx *c = new (std::nothrow) snap_ctx();
+    if (!c) return fail(SNAP_ENOMEM, "host allocation failed");
+    c->prm = *p;
+    try {
+        build_tables(p->twojmax, c->tab);
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return fail(SNAP_ENOMEM, "host allocation failed while building tables");
+    }
+    *out = c;
+    g_err.clear();
+    return SNAP_OK;
+}
+
+int snap_setup(int twojmax, double rcut, double rfac0, double rmin0, int switch_flag, snap_ctx **out)
+{
+    snap_params p;
+    p.twojmax = twojmax;
+    p.rcut = rcut;
+    p.rfac0 = rfac0;
+    p.rmin0 = rmin0;
+    p.switch_flag = switch_flag;
+    p.wself = 1.0;
+    p.dedr_dirs = 0;
+    return snap_setup_ex(&p, out);
+}
+
+int snap_destroy(snap_ctx *c)
+{
+    if (!c) return SNAP_OK;
+    for (auto &u : c->ev_used) {
+        (void)hipEventSynchronize(u.second.second);
+        c->ev_pool.push_back(u.second.first);
+        c->ev_pool.push_back(u.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->dev_ready) free_dev(c);
+    delete c;
+    return SNAP_OK;
+}
+
+int snap_ncoeff(const snap_ctx *c)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    return c->tab.nb;
+}
+
+int snap_nhalf(const snap_ctx *c)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    return c->tab.nhalf;
+}
+
+int snap_table(const snap_ctx *c, int which, void *buf, int cap)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    const Tables &t = c->tab;
+    auto put_int3 = [&](const std::vector<std::array<int, 3>> &v) {
+        int *o = (int *)buf;
+        for (size_t k = 0; k < v.size() && o && (int)(3 * k + 2) < cap; ++k)
+            for (int d = 0; d < 3; ++d) o[3 * k + d] = v[k][d];
+        return (int)(3 * v.size());
+    };
+    switch (which) {
+    case 0: return put_int3(t.comps);
+    case 1: return put_int3(t.helem);
+    case 2: {
+        double *o = (double *)buf;
+        for (size_t k = 0; k < t.cg_vals.size() && o && (int)k < cap; ++k) o[k] = t.cg_vals[k];
+        return (int)t.cg_vals.size();
+    }
+    case 3: {
+        int *o = (int *)buf;
+        for (size_t k = 0; k < t.cg_keys.size() && o && (int)(5 * k + 4) < cap; ++k)
+            for (int d = 0; d < 5; ++d) o[5 * k + d] = t.cg_keys[k][d];
+        return (int)(5 * t.cg_keys.size());
+    }
+    case 4: {
+        const int v[3] = {(int)t.terms.size(), (int)t.items.size(), (int)t.rows.size()};
+        int *o = (int *)buf;
+        for (int k = 0; k < 3 && o && k < cap; ++k) o[k] = v[k];
+        return 3;
+    }
+    default: return fail(SNAP_EINVAL, "unknown table %d", which);
+    }
+}
+
+int snap_build_neighbors(const double *pos_host, int n, const double box[3], double rcut, int *off,
+                         int *nbr, int *rev, int cap, int *npairs)
+{
+    if (n < 0 || !off || !npairs || (n > 0 && !pos_host) || cap < 0 || (cap > 0 && (!nbr || !rev)))
+        return fail(SNAP_EINVAL, "bad arguments to snap_build_neighbors");
+    if (!(rcut > 0.0)) return fail(SNAP_EINVAL, "rcut must be > 0");
+    int st = check_box(box, rcut);
+    if (st) return st;
+    for (long k = 0; k < 3L * n; ++k)
+        if (!std::isfinite(pos_host[k])) return fail(SNAP_EGEOM, "non-finite position");
+    try {
+        if (build_neighbors(pos_host, n, box, rcut, off, nbr, rev, cap, npairs) != 0)
+            return fail(SNAP_ENOMEM, "neighbour capacity %d too small (%d pairs)", cap, *npairs);
+    } catch (const std::bad_alloc &) {
+        return fail(SNAP_ENOMEM, "host allocation failed in the neighbour builder");
+    }
+    return SNAP_OK;
+}
+
+int snap_check_neighbors(int n, const int *off, const int *nbr, const int *rev, int npairs)
+{
+    if (n < 0 || npairs < 0 || !off) return fail(SNAP_EINVAL, "bad arguments");
+    if (off[0] != 0 || off[n] != npairs) return fail(SNAP_ENBR, "off[0] must be 0 and off[n] == npairs");
+    for (int i = 0; i < n; ++i) {
+        if (off[i + 1] < off[i]) return fail(SNAP_ENBR, "off decreases at atom %d", i);
+        for (int p = off[i]; p < off[i + 1]; ++p) {
+            const int k = nbr[p];
+            if (k < 0 || k >= n) return fail(SNAP_ENBR, "neighbour index %d out of range", k);
+            if (k == i) return fail(SNAP_ENBR, "atom %d lists itself", i);
+            const int r = rev[p];
+            if (r < 0 || r >= npairs) return fail(SNAP_ENBR, "rev[%d] = %d out of range", p, r);
+            if (nbr[r] != i || r < off[k] || r >= off[k + 1] || rev[r] != p)
+                return fail(SNAP_ENBR, "rev[%d] does not point at the reverse pair", p);
+        }
+    }
+    return SNAP_OK;
+}
+
+static int common_checks(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                         const int *off, const int *nbr, const int *rev, const double *beta)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    if (n < 0 || npairs < 0) return fail(SNAP_EINVAL, "negative size");
+    if (n > (1 << 24) || npairs > (1 << 30)) return fail(SNAP_EINVAL, "size too large");
+    int st = check_box(box, c->prm.rcut);
+    if (st) return st;
+    if (n > 0 && (!pos || !off || !beta)) return fail(SNAP_EINVAL, "NULL input pointer");
+    if (npairs > 0 && (!nbr || !rev)) return fail(SNAP_EINVAL, "NULL neighbour pointer");
+    return SNAP_OK;
+}
+
+// compute_U (+ pair->atom map) for the current call
+static int run_u(snap_ctx *c, int n, int npairs, const double *pos, const Geom &g, const int *off,
+                 const int *nbr, hipStream_t s)
+{
+    (void)npairs;
+    HIP_TRY(launch_compute_u(c->prm.twojmax, n, c->work.npad, pos, off, nbr, c->dev, g, c->work.U,
+                             c->work.pair_atom, c->work.flag, s),
+            "compute_U launch");
+    return SNAP_OK;
+}
+
+int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                 const int *off, const int *nbr, const int *rev, const double *beta,
+                 int per_atom_beta, double *energy, double *force, double *bispec,
+                 double *dE_pair, void *stream)
+{
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
+    if (st) return st;
+    if (n > 0 && (!energy || !force)) return fail(SNAP_EINVAL, "NULL output pointer");
+    if ((st = ensure_device(c))) return st;
+    if (n == 0) return SNAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
+    const Geom g = make_geom(c, box);
+    Work &w = c->work;
+    const int nb = c->tab.nb, nh = c->tab.nhalf;
+    double *dE = dE_pair ? dE_pair : w.dE;
+    {
+        StageTimer tm(c, 0, s);
+        if ((st = run_u(c, n, npairs, pos, g, off, nbr, s))) return st;
+        tm.finish();
+    }
+    {
+        StageTimer tm(c, 1, s);
+        HIP_TRY(launch_compute_y(n, w.npad, nh, w.U, w.Y, c->dev, beta, per_atom_beta, nb, nullptr,
+                                 s),
+                "compute_Y launch");
+        tm.finish();
+    }
+    if (npairs > 0) {
+        StageTimer tm(c, 2, s);
+        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
+                            w.Y, c->dev, g, dE, s),
+                "compute_dE launch");
+        tm.finish();
+    }
+    {
+        StageTimer tm(c, 3, s);
+        HIP_TRY(launch_gather(n, w.npad, nh, off, rev, dE, w.U, w.Y, energy, force, s),
+                "update_forces launch");
+        tm.finish();
+    }
+    if (bispec) {
+        StageTimer tm(c, 4, s);
+        HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, bispec, beta, per_atom_beta, nullptr,
+                                  s),
+                "bispectrum launch");
+        tm.finish();
+    }
+    c->last_n = n;
+    return SNAP_OK;
+}
+
+int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                 const int *off, const int *nbr, const int *rev, const double *beta,
+                 int per_atom_beta, double *energy, double *bispec, void *stream)
+{
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
+    if (st) return st;
+    if (n > 0 && (!energy || !bispec)) return fail(SNAP_EINVAL, "NULL output pointer");
+    if ((st = ensure_device(c))) return st;
+    if (n == 0) return SNAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
+    const Geom g = make_geom(c, box);
+    if ((st = run_u(c, n, npairs, pos, g, off, nbr, s))) return st;
+    HIP_TRY(launch_bispectrum(n, c->work.npad, c->work.U, c->dev, c->tab.nb, bispec, beta,
+                              per_atom_beta, energy, s),
+            "bispectrum launch");
+    c->last_n = n;
+    return SNAP_OK;
+}
+
+int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                  const int *off, const int *nbr, const int *rev, const double *beta,
+                  int per_atom_beta, const double *grad_energy, double *force, double *dE_pair,
+                  void *stream)
+{
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
+    if (st) return st;
+    if (n > 0 && (!grad_energy || !force)) return fail(SNAP_EINVAL, "NULL gradient pointer");
+    if (n != c->last_n) return fail(SNAP_EINVAL, "snap_backward needs a snap_forward with the same n");
+    if ((st = ensure_device(c))) return st;
+    if (n == 0) return SNAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
+    const Geom g = make_geom(c, box);
+    Work &w = c->work;
+    double *dE = dE_pair ? dE_pair : w.dE;
+    HIP_TRY(launch_compute_y(n, w.npad, c->tab.nhalf, w.U, w.Y, c->dev, beta, per_atom_beta,
+                             c->tab.nb, grad_energy, s),
+            "compute_Y launch");
+    if (npairs > 0)
+        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom, w.Y,
+                            c->dev, g, dE, s),
+                "compute_dE launch");
+    HIP_TRY(launch_gather(n, w.npad, c->tab.nhalf, off, rev, dE, w.U, w.Y, nullptr, force, s),
+            "update_forces launch");
+    return SNAP_OK;
+}
+
+int snap_copy_workspace(snap_ctx *c, int which, double *dst, void *stream)
+{
+    if (!c || !dst || (which != 0 && which != 1)) return fail(SNAP_EINVAL, "bad arguments");
+    if (!c->dev_ready || c->last_n <= 0) return fail(SNAP_EINVAL, "no evaluation to copy from");
+    // the workspace holds scaled values (U/N and w N Y); return true ones
+    const double2 *src = which == 0 ? c->work.U : c->work.Y;
+    const double *scale = which == 0 ? c->dev.unscale_u : c->dev.unscale_y;
+    HIP_TRY(launch_unscale(c->last_n, c->work.npad, c->tab.nhalf, src, scale, dst,
+                           (hipStream_t)stream),
+            "copy workspace");
+    return SNAP_OK;
+}
+
+int snap_profile(snap_ctx *c, int enable)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    c->profiling = enable != 0;
+    return SNAP_OK;
+}
+
+int snap_stage_times(snap_ctx *c, double ms[5], int launches[5])
+{
+    if (!c || !ms || !launches) return fail(SNAP_EINVAL, "bad arguments");
+    for (int k = 0; k < 5; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &u : c->ev_used) {
+        HIP_TRY(hipEventSynchronize(u.second.second), "hipEventSynchronize");
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, u.second.first, u.second.second), "hipEventElapsedTime");
+        ms[u.first] += (double)t;
+        launches[u.first] += 1;
+        c->ev_pool.push_back(u.second.first);
+        c->ev_pool.push_back(u.second.second);
+    }
+    c->ev_used.clear();
+    return SNAP_OK;
+}
+
+int snap_sync_status(snap_ctx *c, void *stream)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    if (!c->dev_ready) return SNAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, c->work.flag, sizeof(int), hipMemcpyDeviceToHost), "read flag");
+    if (flag) {
+        HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
+        return fail(SNAP_EGEOM, "coincident atoms (r < 1e-10 A) or non-finite positions");
+    }
+    return SNAP_OK;
+}
+
+}  // extern "C"

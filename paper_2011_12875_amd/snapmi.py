@@ -1,0 +1,275 @@
+"""Thin Python binding of libsnapmi.so (the C ABI declared in include/snapmi.h).
+
+Argument marshalling only: every stage of the evaluation runs in the HIP
+kernels of the library.  Device buffers are torch tensors on the current
+HIP device and work is enqueued on torch's current stream.  The library must
+have been built (``python -m paper_2011_12875_amd.build``); there is no
+fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnapmi.so")
+
+SNAP_OK = 0
+ERRORS = {-1: "SNAP_EINVAL", -2: "SNAP_EBOX", -3: "SNAP_ENBR", -4: "SNAP_EGEOM",
+          -5: "SNAP_ENOMEM", -6: "SNAP_EDEV"}
+
+# every symbol include/snapmi.h declares
+EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_nhalf",
+           "snap_table", "snap_build_neighbors", "snap_check_neighbors", "snap_compute",
+           "snap_forward", "snap_backward", "snap_copy_workspace", "snap_profile",
+           "snap_stage_times", "snap_sync_status", "snap_last_error"]
+
+
+class SnapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class snap_params(ctypes.Structure):
+    _fields_ = [("twojmax", ctypes.c_int), ("rcut", ctypes.c_double), ("rfac0", ctypes.c_double),
+                ("rmin0", ctypes.c_double), ("switch_flag", ctypes.c_int),
+                ("wself", ctypes.c_double), ("dedr_dirs", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load libsnapmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsnapmi.so is not built: run python -m paper_2011_12875_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    i, d = ctypes.c_int, ctypes.c_double
+    sig = {
+        "snap_setup": (i, [i, d, d, d, i, ctypes.POINTER(vp)]),
+        "snap_setup_ex": (i, [ctypes.POINTER(snap_params), ctypes.POINTER(vp)]),
+        "snap_destroy": (i, [vp]),
+        "snap_ncoeff": (i, [vp]),
+        "snap_nhalf": (i, [vp]),
+        "snap_table": (i, [vp, i, vp, i]),
+        "snap_build_neighbors": (i, [dp, i, dp, d, ip, ip, ip, i, ip]),
+        "snap_check_neighbors": (i, [i, ip, ip, ip, i]),
+        "snap_compute": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp, vp]),
+        "snap_forward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp]),
+        "snap_backward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp]),
+        "snap_copy_workspace": (i, [vp, i, vp, vp]),
+        "snap_sync_status": (i, [vp, vp]),
+        "snap_profile": (i, [vp, i]),
+        "snap_stage_times": (i, [vp, dp, ip]),
+        "snap_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != SNAP_OK:
+        raise SnapError(code, load().snap_last_error().decode())
+    return code
+
+
+def _np_dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _np_ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def build_neighbors(pos, box, rcut):
+    """Host cell-list full neighbour list: (off[n+1], nbr[P], rev[P]) int32."""
+    lib = load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    n = pos.shape[0]
+    cap = max(16, 40 * n)
+    while True:
+        off = np.zeros(n + 1, dtype=np.int32)
+        nbr = np.zeros(cap, dtype=np.int32)
+        rev = np.zeros(cap, dtype=np.int32)
+        npairs = ctypes.c_int(0)
+        st = lib.snap_build_neighbors(_np_dp(pos), n, _np_dp(box), float(rcut), _np_ip(off),
+                                      _np_ip(nbr), _np_ip(rev), cap, ctypes.byref(npairs))
+        if st == -5 and npairs.value > cap:
+            cap = npairs.value
+            continue
+        _check(st)
+        P = npairs.value
+        return off, nbr[:P].copy(), rev[:P].copy()
+
+
+def check_neighbors(off, nbr, rev):
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    rev = np.ascontiguousarray(rev, dtype=np.int32)
+    return _check(load().snap_check_neighbors(len(off) - 1, _np_ip(off), _np_ip(nbr), _np_ip(rev),
+                                              len(nbr)))
+
+
+class NeighborList:
+    """CSR full neighbour list resident on the device (torch int32 tensors)."""
+
+    def __init__(self, off, nbr, rev, device="cuda"):
+        import torch
+        self.n = len(off) - 1
+        self.npairs = len(nbr)
+        self.off = torch.as_tensor(np.asarray(off, dtype=np.int32), device=device)
+        self.nbr = torch.as_tensor(np.asarray(nbr, dtype=np.int32), device=device)
+        self.rev = torch.as_tensor(np.asarray(rev, dtype=np.int32), device=device)
+        if self.npairs == 0:  # keep valid pointers
+            self.nbr = torch.zeros(1, dtype=torch.int32, device=device)
+            self.rev = torch.zeros(1, dtype=torch.int32, device=device)
+
+    @classmethod
+    def build(cls, pos, box, rcut, device="cuda"):
+        off, nbr, rev = build_neighbors(pos, box, rcut)
+        return cls(off, nbr, rev, device)
+
+
+class SnapPotential:
+    """One parameter set of the potential (a library context)."""
+
+    def __init__(self, twojmax, rcut, rfac0=0.99363, rmin0=0.0, switch_flag=1, wself=1.0,
+                 dedr_dirs=0):
+        lib = load()
+        p = snap_params(int(twojmax), float(rcut), float(rfac0), float(rmin0), int(switch_flag),
+                        float(wself), int(dedr_dirs))
+        ctx = ctypes.c_void_p()
+        _check(lib.snap_setup_ex(ctypes.byref(p), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self.twojmax = int(twojmax)
+        self.rcut = float(rcut)
+        self.ncoeff = lib.snap_ncoeff(ctx)
+        self.nhalf = lib.snap_nhalf(ctx)
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and _lib is not None:
+            _lib.snap_destroy(ctx)
+            self._ctx = None
+
+    # -- tables ------------------------------------------------------------
+    def table(self, which):
+        lib = load()
+        n = lib.snap_table(self._ctx, which, None, 0)
+        _check(0 if n >= 0 else n)
+        dtype = np.float64 if which == 2 else np.int32
+        buf = np.zeros(max(n, 1), dtype=dtype)
+        lib.snap_table(self._ctx, which, buf.ctypes.data_as(ctypes.c_void_p), n)
+        buf = buf[:n]
+        if which in (0, 1):
+            return buf.reshape(-1, 3)
+        if which == 3:
+            return buf.reshape(-1, 5)
+        return buf
+
+    def program_size(self):
+        """(Clebsch-Gordan terms, Z items, Y rows) of the contraction program."""
+        return tuple(int(x) for x in self.table(4))
+
+    STAGES = ("compute_U", "compute_Y", "compute_dE", "update_forces", "bispectrum")
+
+    def profile(self, enable=True):
+        _check(load().snap_profile(self._ctx, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: (summed ms, launches)} since the last call (waits for them)."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int * 5)()
+        _check(load().snap_stage_times(self._ctx, ms, cnt))
+        return {self.STAGES[k]: (ms[k], cnt[k]) for k in range(5)}
+
+    # -- evaluation ----------------------------------------------------------
+    @staticmethod
+    def _stream():
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    @staticmethod
+    def _ptr(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    def _args(self, pos, box, nl, beta):
+        import torch
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+        assert beta.dtype == torch.float64 and beta.is_cuda and beta.is_contiguous()
+        n = pos.shape[0]
+        assert nl.n == n
+        per_atom = 1 if beta.dim() == 2 else 0
+        if per_atom:
+            assert beta.shape == (n, self.ncoeff)
+        else:
+            assert beta.shape == (self.ncoeff,)
+        boxa = (ctypes.c_double * 3)(*[float(x) for x in box])
+        return n, boxa, per_atom
+
+    def compute(self, pos, box, nl, beta, bispectrum=False, pair_derivs=False, out=None):
+        """E_i and F_i (and optionally B_i and dE per pair), as torch tensors."""
+        import torch
+        n, boxa, per_atom = self._args(pos, box, nl, beta)
+        dev = pos.device
+        if out is None:
+            out = {}
+            out["energy"] = torch.empty(n, dtype=torch.float64, device=dev)
+            out["force"] = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            if bispectrum:
+                out["bispectrum"] = torch.empty((n, self.ncoeff), dtype=torch.float64, device=dev)
+            if pair_derivs:
+                out["dE"] = torch.empty((max(nl.npairs, 1), 3), dtype=torch.float64, device=dev)
+        _check(load().snap_compute(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(out["energy"]),
+            self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
+            self._stream()))
+        return out
+
+    def forward(self, pos, box, nl, beta):
+        """compute_U + bispectrum: (E_i, B_i); keeps U for backward()."""
+        import torch
+        n, boxa, per_atom = self._args(pos, box, nl, beta)
+        E = torch.empty(n, dtype=torch.float64, device=pos.device)
+        B = torch.empty((n, self.ncoeff), dtype=torch.float64, device=pos.device)
+        _check(load().snap_forward(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(E), self._ptr(B),
+            self._stream()))
+        return E, B
+
+    def backward(self, pos, box, nl, beta, grad_energy):
+        """-d(sum_i g_i E_i)/dr (the forces of the weighted energy)."""
+        import torch
+        n, boxa, per_atom = self._args(pos, box, nl, beta)
+        g = grad_energy.contiguous()
+        assert g.dtype == torch.float64 and g.shape == (n,)
+        F = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        _check(load().snap_backward(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(g), self._ptr(F), None,
+            self._stream()))
+        return F
+
+    def workspace(self, which, n):
+        """True U_j (which=0) or Y_j (which=1) of the last call: [nhalf, n] complex."""
+        import torch
+        dst = torch.empty((self.nhalf, n, 2), dtype=torch.float64, device="cuda")
+        _check(load().snap_copy_workspace(self._ctx, which, self._ptr(dst), self._stream()))
+        return torch.view_as_complex(dst)
+
+    def sync_status(self):
+        return _check(load().snap_sync_status(self._ctx, self._stream()))
