@@ -49,14 +49,14 @@ def _element_costs(twojmax):
     return nel, u, du
 
 
-def algorithmic_flops(twojmax, natoms, npairs, nterms, nitems):
+def algorithmic_flops(twojmax, natoms, npairs, nterms, npartials):
     nel, u_rec, du_rec = _element_costs(twojmax)
     flops = {
         # recursion + f_c weighting (2/element) + per-atom sum (2/element)
         "compute_U": npairs * (u_rec + 4 * nel),
-        # 10 per Clebsch-Gordan term (complex product, real weight, accumulate)
-        # and 6 per Z element (coefficient times Z into Y)
-        "compute_Y": natoms * (10 * nterms + 6 * nitems),
+        # 10 per Clebsch-Gordan product (complex product, real weight,
+        # accumulate) and 4 per partial sum (row coefficient times the sum)
+        "compute_Y": natoms * (10 * nterms + 4 * npartials),
         # u once, du for three directions, four dot products with Y, and
         # dE = f_c' n S0 + f_c S per direction
         "compute_dE": npairs * (u_rec + 3 * du_rec + 16 * nel + 9),
@@ -78,8 +78,9 @@ def algorithmic_bytes(twojmax, natoms, npairs, nhalf):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("snap_kernels.hip", "snap_tables.cpp", "snap_abi.cpp"):
-        with open(os.path.join(ROOT, "paper_2011_12875_amd", "csrc", f), "rb") as fh:
+    d = os.path.join(ROOT, "paper_2011_12875_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -175,8 +176,8 @@ def main():
     pot.profile(False)
     avg_ms = {k: v[0] / v[1] for k, v in stages.items() if v[1] > 0}
 
-    nterms, nitems, _ = pot.program_size()
-    flops = algorithmic_flops(tj, n, nl.npairs, nterms, nitems)
+    nterms, npartials, _, _ = pot.program_size()
+    flops = algorithmic_flops(tj, n, nl.npairs, nterms, npartials)
     hbm = algorithmic_bytes(tj, n, nl.npairs, pot.nhalf)
     dominant = max(("compute_U", "compute_Y", "compute_dE"), key=lambda k: avg_ms.get(k, 0.0))
     achieved = flops[dominant] / (avg_ms[dominant] * 1e-3) / 1e12

@@ -97,8 +97,9 @@ int snap_nhalf(const snap_ctx *c);
  *   2: Clebsch-Gordan values used on the device, double, one per
  *      (J1, J2, J, M1, M2) in the order of snap_table(3)
  *   3: the keys of table 2, int[5 * count]
- *   4: sizes of the contraction program, int[3]: Clebsch-Gordan terms, Z
- *      items and Y rows (the work of compute_Y per atom)
+ *   4: sizes of the compute_Y program per atom, int[4]: Clebsch-Gordan
+ *      products, partial sums (contribution, row, column), contributions
+ *      and rows of Y
  * buf has room for cap elements of the table's type; returns the number of
  * elements of the table (which may exceed cap: nothing beyond cap is
  * written), or SNAP_EINVAL. */

@@ -104,17 +104,22 @@ static hipError_t upload(T *&dst, const std::vector<T> &src)
 static void free_dev(snap_ctx *c)
 {
     DevTables &d = c->dev;
-    (void)hipFree(d.unscale_u);
     (void)hipFree(d.unscale_y);
-    (void)hipFree(d.terms);
-    (void)hipFree(d.items);
-    (void)hipFree(d.rows);
+    (void)hipFree(d.half2full);
+    (void)hipFree(d.uinfo);
+    (void)hipFree(d.bterms);
     (void)hipFree(d.bitems);
     (void)hipFree(d.bl_begin);
+    (void)hipFree(d.ycontrib);
+    (void)hipFree(d.yrows);
+    (void)hipFree(d.ycp);
+    (void)hipFree(d.ycq);
+    (void)hipFree(d.nfull);
     d = DevTables();
     Work &w = c->work;
     (void)hipFree(w.U);
     (void)hipFree(w.Y);
+    (void)hipFree(w.Epart);
     (void)hipFree(w.dE);
     (void)hipFree(w.pair_atom);
     (void)hipFree(w.flag);
@@ -135,14 +140,18 @@ static int ensure_device(snap_ctx *c)
                     prop.gcnArchName);
     const Tables &t = c->tab;
     DevTables &d = c->dev;
-    HIP_TRY(upload(d.unscale_u, t.unscale_u), "upload unscale_u");
     HIP_TRY(upload(d.unscale_y, t.unscale_y), "upload unscale_y");
-    HIP_TRY(upload(d.terms, t.terms), "upload terms");
-    HIP_TRY(upload(d.items, t.items), "upload items");
-    HIP_TRY(upload(d.rows, t.rows), "upload rows");
+    HIP_TRY(upload(d.half2full, t.half2full), "upload half2full");
+    HIP_TRY(upload(d.uinfo, t.uinfo), "upload uinfo");
+    HIP_TRY(upload(d.bterms, t.bterms), "upload bterms");
     HIP_TRY(upload(d.bitems, t.bitems), "upload bitems");
     HIP_TRY(upload(d.bl_begin, t.bl_begin), "upload bl_begin");
-    d.nrows = (int)t.rows.size();
+    HIP_TRY(upload(d.ycontrib, t.ycontrib), "upload ycontrib");
+    HIP_TRY(upload(d.yrows, t.yrows), "upload yrows");
+    HIP_TRY(upload(d.ycp, t.ycp), "upload ycp");
+    HIP_TRY(upload(d.ycq, t.ycq), "upload ycq");
+    HIP_TRY(upload(d.nfull, t.nfull), "upload nfull");
+    d.nyrows = (int)t.yrows.size();
     HIP_TRY(hipMalloc((void **)&c->work.flag, sizeof(int)), "alloc flag");
     HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
     c->device = dev;
@@ -162,11 +171,16 @@ static int ensure_work(snap_ctx *c, int n, int np, hipStream_t s)
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         (void)hipFree(w.U);
         (void)hipFree(w.Y);
+        (void)hipFree(w.Epart);
         w.U = w.Y = nullptr;
+        w.Epart = nullptr;
         c->cap_atoms = 0;
-        HIP_TRY(hipMalloc((void **)&w.U, sizeof(double2) * nh * npad), "alloc U");
+        HIP_TRY(hipMalloc((void **)&w.U, sizeof(double2) * (size_t)c->tab.nfullel * npad),
+                "alloc U");
         HIP_TRY(hipMalloc((void **)&w.Y, sizeof(double2) * nh * npad), "alloc Y");
-        HIP_TRY(hipMemset(w.U, 0, sizeof(double2) * nh * npad), "clear U");
+        HIP_TRY(hipMalloc((void **)&w.Epart, sizeof(double) * c->tab.yrows.size() * npad),
+                "alloc Epart");
+        HIP_TRY(hipMemset(w.U, 0, sizeof(double2) * (size_t)c->tab.nfullel * npad), "clear U");
         HIP_TRY(hipMemset(w.Y, 0, sizeof(double2) * nh * npad), "clear Y");
         c->cap_atoms = npad;
     }
@@ -321,10 +335,11 @@ int snap_table(const snap_ctx *c, int which, void *buf, int cap)
         return (int)(5 * t.cg_keys.size());
     }
     case 4: {
-        const int v[3] = {(int)t.terms.size(), (int)t.items.size(), (int)t.rows.size()};
+        const int v[4] = {(int)t.yterms, (int)t.ypartials, (int)t.ycontrib.size(),
+                          (int)t.yrows.size()};
         int *o = (int *)buf;
-        for (int k = 0; k < 3 && o && k < cap; ++k) o[k] = v[k];
-        return 3;
+        for (int k = 0; k < 4 && o && k < cap; ++k) o[k] = v[k];
+        return 4;
     }
     default: return fail(SNAP_EINVAL, "unknown table %d", which);
     }
@@ -406,7 +421,7 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
     if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
     const Geom g = make_geom(c, box);
     Work &w = c->work;
-    const int nb = c->tab.nb, nh = c->tab.nhalf;
+    const int nb = c->tab.nb;
     double *dE = dE_pair ? dE_pair : w.dE;
     {
         StageTimer tm(c, 0, s);
@@ -415,8 +430,8 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
     }
     {
         StageTimer tm(c, 1, s);
-        HIP_TRY(launch_compute_y(n, w.npad, nh, w.U, w.Y, c->dev, beta, per_atom_beta, nb, nullptr,
-                                 s),
+        HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, beta, per_atom_beta,
+                                 nb, nullptr, w.Epart, s),
                 "compute_Y launch");
         tm.finish();
     }
@@ -429,7 +444,7 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
     }
     {
         StageTimer tm(c, 3, s);
-        HIP_TRY(launch_gather(n, w.npad, nh, off, rev, dE, w.U, w.Y, energy, force, s),
+        HIP_TRY(launch_gather(n, w.npad, c->dev.nyrows, off, rev, dE, w.Epart, energy, force, s),
                 "update_forces launch");
         tm.finish();
     }
@@ -480,14 +495,14 @@ int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const doubl
     const Geom g = make_geom(c, box);
     Work &w = c->work;
     double *dE = dE_pair ? dE_pair : w.dE;
-    HIP_TRY(launch_compute_y(n, w.npad, c->tab.nhalf, w.U, w.Y, c->dev, beta, per_atom_beta,
-                             c->tab.nb, grad_energy, s),
+    HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, beta, per_atom_beta,
+                             c->tab.nb, grad_energy, nullptr, s),
             "compute_Y launch");
     if (npairs > 0)
         HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom, w.Y,
                             c->dev, g, dE, s),
                 "compute_dE launch");
-    HIP_TRY(launch_gather(n, w.npad, c->tab.nhalf, off, rev, dE, w.U, w.Y, nullptr, force, s),
+    HIP_TRY(launch_gather(n, w.npad, c->dev.nyrows, off, rev, dE, nullptr, nullptr, force, s),
             "update_forces launch");
     return SNAP_OK;
 }
@@ -498,8 +513,9 @@ int snap_copy_workspace(snap_ctx *c, int which, double *dst, void *stream)
     if (!c->dev_ready || c->last_n <= 0) return fail(SNAP_EINVAL, "no evaluation to copy from");
     // the workspace holds scaled values (U/N and w N Y); return true ones
     const double2 *src = which == 0 ? c->work.U : c->work.Y;
-    const double *scale = which == 0 ? c->dev.unscale_u : c->dev.unscale_y;
-    HIP_TRY(launch_unscale(c->last_n, c->work.npad, c->tab.nhalf, src, scale, dst,
+    const int *map = which == 0 ? c->dev.half2full : nullptr;
+    const double *scale = which == 0 ? nullptr : c->dev.unscale_y;
+    HIP_TRY(launch_unscale(c->last_n, c->work.npad, c->tab.nhalf, src, map, scale, dst,
                            (hipStream_t)stream),
             "copy workspace");
     return SNAP_OK;

@@ -15,20 +15,25 @@ struct Geom {
 
 // Device copies of the tables of one context.
 struct DevTables {
-    double *unscale_u = nullptr, *unscale_y = nullptr;
-    Term *terms = nullptr;
-    ZItem *items = nullptr;
-    YRow *rows = nullptr;
+    double *unscale_y = nullptr;
+    int *half2full = nullptr;
+    UInfo *uinfo = nullptr;
+    BTerm *bterms = nullptr;
     BItem *bitems = nullptr;
     int *bl_begin = nullptr;
-    int nrows = 0;
+    YContrib *ycontrib = nullptr;
+    YRowC *yrows = nullptr;
+    double *ycp = nullptr, *ycq = nullptr, *nfull = nullptr;
+    int nyrows = 0;
 };
 
 // Per-call device workspace.  Per-atom arrays are element-major:
-// X[e * npad + atom], npad = n rounded up to 64.
+// X[e * npad + atom], npad = n rounded up to 64.  U holds full matrices
+// (sum (J+1)^2 elements), Y the scaled stored half.
 struct Work {
     double2 *U = nullptr, *Y = nullptr;
     double *dE = nullptr;
+    double *Epart = nullptr;  // [nyrows][npad] per-row shares of the energy
     int *pair_atom = nullptr;
     int *flag = nullptr;
     int npad = 0;
@@ -38,24 +43,35 @@ hipError_t launch_compute_u(int twojmax, int n, int npad, const double *pos, con
                             const int *nbr, const DevTables &T, const Geom &g, double2 *U,
                             int *pair_atom, int *flag, hipStream_t s);
 
-hipError_t launch_compute_y(int n, int npad, int nhalf, const double2 *U, double2 *Y,
+hipError_t launch_compute_y(int twojmax, int n, int npad, const double2 *U, double2 *Y,
                             const DevTables &T, const double *beta, int per_atom_beta, int nb,
-                            const double *gscale, hipStream_t s);
+                            const double *gscale, double *Epart, hipStream_t s);
 
 hipError_t launch_bispectrum(int n, int npad, const double2 *U, const DevTables &T, int nb,
                              double *B, const double *beta, int per_atom_beta, double *energy,
                              hipStream_t s);
 
-hipError_t launch_dedr(int twojmax, int dirs, int npairs, int npad, const double *pos,
-                       const int *nbr, const int *pair_atom, const double2 *Y, const DevTables &T,
-                       const Geom &g, double *dE, hipStream_t s);
+hipError_t launch_dedr_low(int twojmax, int dirs, int npairs, int npad, const double *pos,
+                           const int *nbr, const int *pair_atom, const double2 *Y,
+                           const DevTables &T, const Geom &g, double *dE, hipStream_t s);
+hipError_t launch_dedr_high(int twojmax, int dirs, int npairs, int npad, const double *pos,
+                            const int *nbr, const int *pair_atom, const double2 *Y,
+                            const DevTables &T, const Geom &g, double *dE, hipStream_t s);
+inline hipError_t launch_dedr(int twojmax, int dirs, int npairs, int npad, const double *pos,
+                              const int *nbr, const int *pair_atom, const double2 *Y,
+                              const DevTables &T, const Geom &g, double *dE, hipStream_t s)
+{
+    return twojmax <= 8
+               ? launch_dedr_low(twojmax, dirs, npairs, npad, pos, nbr, pair_atom, Y, T, g, dE, s)
+               : launch_dedr_high(twojmax, dirs, npairs, npad, pos, nbr, pair_atom, Y, T, g, dE, s);
+}
 
-hipError_t launch_gather(int n, int npad, int nhalf, const int *off, const int *rev,
-                         const double *dE, const double2 *U, const double2 *Y, double *energy,
-                         double *force, hipStream_t s);
+hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *rev,
+                         const double *dE, const double *Epart, double *energy, double *force,
+                         hipStream_t s);
 
-// dst[e][atom][re/im] = scale[e] * src[e * npad + atom] for atom < n
-hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const double *scale,
-                          double *dst, hipStream_t s);
+// dst[e][atom][re/im] = scale[e] * src[map[e] * npad + atom] for atom < n
+hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const int *map,
+                          const double *scale, double *dst, hipStream_t s);
 
 }  // namespace snapmi

@@ -1,0 +1,144 @@
+// snap_misc.hip -- bispectrum (eq. (z)), energies, update_forces and workspace copies.
+#include "snap_device.hpp"
+
+namespace snapmi {
+
+namespace {
+using namespace dev;
+
+// ---------------------------------------------------------------------------
+// bispectrum (eq. (z)) and energy (eq. (snapatomenergy)) -- lanes are atoms
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_bispectrum(int n, int npad, const double2 *__restrict__ U,
+                                                   const BTerm *__restrict__ terms,
+                                                   const BItem *__restrict__ bitems,
+                                                   const int *__restrict__ bl_begin, int nb,
+                                                   double *__restrict__ B)
+{
+    const int l = blockIdx.y;
+    const int atom = blockIdx.x * 64 + threadIdx.x;
+    const double2 *Ua = U + atom;
+    double bsum = 0.0;
+    const int xe = bl_begin[l + 1];
+    for (int x = bl_begin[l]; x < xe; ++x) {
+        const BItem *bi = bitems + x;
+        double zr = 0.0, zi = 0.0;
+        const int te = bi->te;
+        for (int tt = bi->tb; tt < te; ++tt) {
+            const BTerm tm = terms[tt];
+            const double2 u1 = Ua[(size_t)tm.f1 * npad];
+            const double2 u2 = Ua[(size_t)tm.f2 * npad];
+            zr += tm.cc * (u1.x * u2.x - u1.y * u2.y);
+            zi += tm.cc * (u1.x * u2.y + u1.y * u2.x);
+        }
+        const double2 uj = Ua[(size_t)bi->f3 * npad];
+        bsum += bi->w * (zr * uj.x + zi * uj.y);
+    }
+    if (atom < n) B[(size_t)atom * nb + l] = bsum;
+}
+
+__global__ void k_energy_from_b(int n, int nb, const double *__restrict__ B,
+                                const double *__restrict__ beta, int per_atom_beta,
+                                double *__restrict__ energy)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *bt = per_atom_beta ? beta + (size_t)i * nb : beta;
+    double e = 0.0;
+    for (int l = 0; l < nb; ++l) e += bt[l] * B[(size_t)i * nb + l];
+    energy[i] = e;
+}
+
+// ---------------------------------------------------------------------------
+// update_forces and the energy
+// ---------------------------------------------------------------------------
+// Eight lanes per atom: the lanes stride over the atom's pairs (forces) and
+// over the row partials of the energy, then combine with shuffles in a fixed
+// order.
+__global__ __launch_bounds__(256) void k_gather(int n, int npad, int nrows,
+                                                const int *__restrict__ off,
+                                                const int *__restrict__ rev,
+                                                const double *__restrict__ dE,
+                                                const double *__restrict__ Epart,
+                                                double *__restrict__ energy,
+                                                double *__restrict__ force)
+{
+    const int g = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const int s = threadIdx.x & 7;
+    const int i = g < n ? g : n - 1;
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+    const int te = off[i + 1];
+    for (int t = off[i] + s; t < te; t += 8) {
+        const int r = rev[t];
+        fx += dE[3 * (size_t)t + 0] - dE[3 * (size_t)r + 0];
+        fy += dE[3 * (size_t)t + 1] - dE[3 * (size_t)r + 1];
+        fz += dE[3 * (size_t)t + 2] - dE[3 * (size_t)r + 2];
+    }
+    if (energy)
+        for (int k = s; k < nrows; k += 8) e += Epart[(size_t)k * npad + i];
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        fx += __shfl_xor(fx, m, 8);
+        fy += __shfl_xor(fy, m, 8);
+        fz += __shfl_xor(fz, m, 8);
+        e += __shfl_xor(e, m, 8);
+    }
+    if (g < n && s == 0) {
+        force[3 * (size_t)g + 0] = fx;
+        force[3 * (size_t)g + 1] = fy;
+        force[3 * (size_t)g + 2] = fz;
+        if (energy) energy[g] = e * (1.0 / 3.0);
+    }
+}
+
+// dst[e][i] = scale[e] * src[map[e] * npad + i] (map, scale optional)
+__global__ void k_unscale(int n, int npad, int nhalf, const double2 *__restrict__ src,
+                          const int *__restrict__ map, const double *__restrict__ scale,
+                          double *__restrict__ dst)
+{
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (size_t)n * nhalf) return;
+    const int e = (int)(k / n), i = (int)(k - (size_t)e * n);
+    const int row = map ? map[e] : e;
+    const double sc = scale ? scale[e] : 1.0;
+    const double2 v = src[(size_t)row * npad + i];
+    dst[2 * k + 0] = sc * v.x;
+    dst[2 * k + 1] = sc * v.y;
+}
+
+}  // namespace
+
+hipError_t launch_bispectrum(int n, int npad, const double2 *U, const DevTables &T, int nb,
+                             double *B, const double *beta, int per_atom_beta, double *energy,
+                             hipStream_t s)
+{
+    const int nblk = (n + 63) / 64;
+    hipLaunchKernelGGL(k_bispectrum, dim3(nblk, nb), dim3(64), 0, s, n, npad, U, T.bterms,
+                       T.bitems, T.bl_begin, nb, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !energy) return e;
+    hipLaunchKernelGGL(k_energy_from_b, dim3((n + 127) / 128), dim3(128), 0, s, n, nb, B, beta,
+                       per_atom_beta, energy);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *rev,
+                         const double *dE, const double *Epart, double *energy, double *force,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather, dim3((n + 31) / 32), dim3(256), 0, s, n, npad, nrows, off, rev,
+                       dE, Epart, energy, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const int *map,
+                          const double *scale, double *dst, hipStream_t s)
+{
+    const size_t tot = (size_t)n * nhalf;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unscale, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, npad,
+                       nhalf, src, map, scale, dst);
+    return hipGetLastError();
+}
+
+}  // namespace snapmi

@@ -50,30 +50,47 @@ void build_tables(int tj, Tables &t)
 {
     t = Tables();
     t.twojmax = tj;
+    auto nrm = [](int J, int p, int q) {
+        // N = sqrt(p!(J-p)!/(q!(J-q)!)): u^J = N * (polynomial coefficient)
+        return std::sqrt(std::exp(std::lgamma(p + 1.0) + std::lgamma(J - p + 1.0) -
+                                  std::lgamma(q + 1.0) - std::lgamma(J - q + 1.0)));
+    };
 
-    // half-matrix storage: for each J, columns q = 0..J/2, rows p = 0..J
+    // half-matrix storage: for each J, columns q = 0..J/2, rows p = 0..J;
+    // full storage: for each J, rows p, columns q = 0..J
     t.hbase.assign(tj + 2, 0);
-    for (int J = 0; J <= tj; ++J) t.hbase[J + 1] = t.hbase[J] + (J + 1) * (J / 2 + 1);
+    t.fbase.assign(tj + 2, 0);
+    for (int J = 0; J <= tj; ++J) {
+        t.hbase[J + 1] = t.hbase[J] + (J + 1) * (J / 2 + 1);
+        t.fbase[J + 1] = t.fbase[J] + (J + 1) * (J + 1);
+    }
     t.nhalf = t.hbase[tj + 1];
+    t.nfullel = t.fbase[tj + 1];
     t.helem.resize(t.nhalf);
     t.norm.assign(t.nhalf, 0.0);
     t.whalf.assign(t.nhalf, 0.0);
-    t.unscale_u.assign(t.nhalf, 0.0);
     t.unscale_y.assign(t.nhalf, 0.0);
+    t.half2full.assign(t.nhalf, 0);
+    t.uinfo.resize(t.nhalf);
     for (int J = 0; J <= tj; ++J)
         for (int q = 0; q <= J / 2; ++q)
             for (int p = 0; p <= J; ++p) {
                 const int e = t.half_index(J, p, q);
                 t.helem[e] = {J, p, q};
-                // u^J_{pq} = N_e poly^J_{pq}; the polynomial coefficients obey
-                // eq. (hysphrecur) along a column with unit weights:
-                //   poly^J_{pq} = a* poly^{J-1}_{pq} - b* poly^{J-1}_{p-1,q}
-                t.norm[e] = std::sqrt(std::exp(std::lgamma(p + 1.0) + std::lgamma(J - p + 1.0) -
-                                               std::lgamma(q + 1.0) - std::lgamma(J - q + 1.0)));
+                t.norm[e] = nrm(J, p, q);
                 t.whalf[e] = (2 * q < J) ? 2.0 : 1.0;
-                t.unscale_u[e] = t.norm[e];
                 t.unscale_y[e] = 1.0 / (t.whalf[e] * t.norm[e]);
+                t.half2full[e] = t.full_index(J, p, q);
+                UInfo ui;
+                ui.fi = t.full_index(J, p, q);
+                ui.fm = (J - p == p && J - q == q) ? -1 : t.full_index(J, J - p, J - q);
+                ui.nrm = t.norm[e];
+                ui.msign = ((p - q) % 2 == 0) ? 1.0 : -1.0;
+                t.uinfo[e] = ui;
             }
+    for (int J = 0; J <= tj; ++J)
+        for (int p = 0; p <= J; ++p)
+            for (int q = 0; q <= J; ++q) t.nfull.push_back(nrm(J, p, q));
 
     // canonical components: J2 <= J1 <= J (Sec. II.A), coupling rules
     std::vector<int> cidx((tj + 1) * (tj + 1) * (tj + 1), -1);
@@ -87,7 +104,7 @@ void build_tables(int tj, Tables &t)
                 }
     t.nb = (int)t.comps.size();
 
-    // Clebsch-Gordan cache keyed by (J1, J2, J, M1, M2)
+    // Clebsch-Gordan values keyed by (J1, J2, J, M1, M2)
     auto cg = [&](int J1, int M1, int J2, int M2, int J) {
         return clebsch_gordan(J1, M1, J2, M2, J, M1 + M2);
     };
@@ -101,142 +118,136 @@ void build_tables(int tj, Tables &t)
                             t.cg_vals.push_back(cg(J1, M1, J2, M2, J));
                         }
 
-    // Operand of a product: the full element (Jx, px, qx) of U (or Y) read
-    // from the stored half; elements with qx > Jx/2 come from the mirror
-    // (Jx-px, Jx-qx) conjugated, with sign (-1)^(qx-px).
-    // The operand's scale N_e (U = N U~) is folded into its sign.
-    struct Operand { int e; bool conj; double sign; };
-    auto operand = [&](int Jx, int px, int qx) -> Operand {
-        if (2 * qx <= Jx) {
-            const int e = t.half_index(Jx, px, qx);
-            return {e, false, t.norm[e]};
-        }
-        const int sgn = ((qx - px) % 2 == 0) ? 1 : -1;
-        const int e = t.half_index(Jx, Jx - px, Jx - qx);
-        return {e, true, (double)sgn * t.norm[e]};
-    };
-
     // The adjoint of eq. (y).  For a canonical l = (J1, J2, J) the derivative
     // of B_l = Z^J_{J1J2} : conj(U^J) with respect to each of its three
     // matrix factors is Re[X : conj(dU)] with X = Z^J_{J1J2} for U^J,
     // (J+1)/(J1+1) Z^{J1}_{J J2} for U^J1 and (J+1)/(J2+1) Z^{J2}_{J J1} for
-    // U^J2 (Clebsch-Gordan symmetry).  So a stored product Z^c_{ab} (a >= b)
-    // enters Y^c with beta_l times (number of factors of rank c in l) times
+    // U^J2 (Clebsch-Gordan symmetry).  So a product Z^c_{ab} (a >= b) enters
+    // Y^c with beta_l times (number of factors of rank c in l) times
     // (J_max+1)/(c+1), where l is the sorted triple {a, b, c}.
-    struct PendingRow { YRow row; std::vector<int> order; std::vector<ZItem> items; std::vector<std::vector<Term>> terms; };
-    std::vector<PendingRow> pend;
-
-    for (int J = 0; J <= tj; ++J)
-        for (int p = 0; p <= J; ++p) {
-            PendingRow pr;
-            pr.row.J = J;
-            pr.row.p = p;
-            pr.row.nq = J / 2 + 1;
-            pr.row.ebase = t.half_index(J, p, 0);
-            for (int a = 0; a <= tj; ++a)
-                for (int b = 0; b <= a; ++b) {
-                    if (J < a - b || J > a + b || (a + b + J) % 2) continue;
-                    int s[3] = {a, b, J};
-                    std::sort(s, s + 3);
-                    const int l = cix(s[1], s[0], s[2]);
-                    const int mult = (a == J) + (b == J) + 1;
-                    const double factor = (double)mult * (double)(s[2] + 1) / (double)(J + 1);
-                    const int M = 2 * p - J;
-                    for (int q = 0; q <= J / 2; ++q) {
-                        const int Mq = 2 * q - J;
-                        const int eo = t.half_index(J, p, q);
-                        const double oscale = t.whalf[eo] * t.norm[eo];  // Y~ = w N Y
-                        std::vector<Term> pat[4];
-                        for (int p1 = 0; p1 <= a; ++p1) {
-                            const int M1 = 2 * p1 - a, M2 = M - M1;
-                            if (std::abs(M2) > b) continue;
-                            const int p2 = (M2 + b) / 2;
-                            const double cp = cg(a, M1, b, M2, J);
-                            if (std::fabs(cp) < 1e-15) continue;
-                            for (int q1 = 0; q1 <= a; ++q1) {
-                                const int N1 = 2 * q1 - a, N2 = Mq - N1;
-                                if (std::abs(N2) > b) continue;
-                                const int q2 = (N2 + b) / 2;
-                                const double cq = cg(a, N1, b, N2, J);
-                                if (std::fabs(cq) < 1e-15) continue;
-                                const Operand o1 = operand(a, p1, q1), o2 = operand(b, p2, q2);
-                                const int k = (o1.conj ? 1 : 0) | (o2.conj ? 2 : 0);
-                                pat[k].push_back({cp * cq * o1.sign * o2.sign * oscale, o1.e, o2.e});
-                            }
-                        }
-                        ZItem it{};
-                        it.q = q;
-                        it.l = l;
-                        it.factor = factor;
-                        it.j1 = a;
-                        it.j2 = b;
-                        std::vector<Term> flat;
-                        it.tb[0] = 0;
-                        for (int k = 0; k < 4; ++k) {
-                            flat.insert(flat.end(), pat[k].begin(), pat[k].end());
-                            it.tb[k + 1] = (int)flat.size();
-                        }
-                        pr.items.push_back(it);
-                        pr.terms.push_back(std::move(flat));
+    {
+        struct PendingC { YRowC row; std::vector<YContrib> cs; };
+        std::vector<PendingC> rows;
+        std::vector<int> cq_at((tj + 1) * (tj + 1) * (tj + 1), -1);
+        auto cqix = [&](int a, int b, int c) -> int & { return cq_at[(a * (tj + 1) + b) * (tj + 1) + c]; };
+        for (int J = 0; J <= tj; ++J)
+            for (int p = 0; p <= J; ++p) {
+                PendingC pr;
+                pr.row.J = J;
+                pr.row.p = p;
+                pr.row.nq = J / 2 + 1;
+                pr.row.ebase = t.half_index(J, p, 0);
+                pr.row.frow = t.full_index(J, p, 0);
+                for (int q = 0; q < 8; ++q) {
+                    if (q < pr.row.nq) {
+                        const int e = t.half_index(J, p, q);
+                        pr.row.oscale[q] = t.whalf[e] * t.norm[e];
+                        pr.row.einv[q] = 1.0 / t.norm[e];
+                    } else {
+                        pr.row.oscale[q] = pr.row.einv[q] = 0.0;
                     }
                 }
-            // longest-processing-time assignment of items to the waves
-            std::vector<int> ord(pr.items.size());
-            std::iota(ord.begin(), ord.end(), 0);
-            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-                return pr.terms[x].size() > pr.terms[y].size();
-            });
-            std::vector<int> load(kYWaves, 0);
-            std::vector<std::vector<int>> wav(kYWaves);
-            for (int x : ord) {
-                const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                wav[w].push_back(x);
-                load[w] += (int)pr.terms[x].size() + 8;
+                const int M = 2 * p - J;
+                for (int a = 0; a <= tj; ++a)
+                    for (int b = 0; b <= a; ++b) {
+                        if (J < a - b || J > a + b || (a + b + J) % 2) continue;
+                        int s3[3] = {a, b, J};
+                        std::sort(s3, s3 + 3);
+                        YContrib c{};
+                        c.j1 = a;
+                        c.j2 = b;
+                        c.d = (a + b - J) / 2;
+                        c.l = cix(s3[1], s3[0], s3[2]);
+                        c.factor = (double)((a == J) + (b == J) + 1) * (double)(s3[2] + 1) / (double)(J + 1);
+                        // valid rows: p2 = p - p1 + d in [0, b]
+                        c.p1lo = std::max(0, p + c.d - b);
+                        c.p1hi = std::min(a, p + c.d);
+                        if (c.p1lo > c.p1hi) continue;
+                        c.cp_off = (int)t.ycp.size();
+                        for (int p1 = c.p1lo; p1 <= c.p1hi; ++p1) {
+                            const int M1 = 2 * p1 - a;
+                            t.ycp.push_back(cg(a, M1, b, M - M1, J));
+                        }
+                        if (cqix(a, b, J) < 0) {
+                            cqix(a, b, J) = (int)t.ycq.size();
+                            for (int q = 0; q <= J / 2; ++q)
+                                for (int q1 = 0; q1 <= a; ++q1) {
+                                    const int N1 = 2 * q1 - a, N2 = (2 * q - J) - N1;
+                                    t.ycq.push_back(std::abs(N2) <= b ? cg(a, N1, b, N2, J) : 0.0);
+                                }
+                        }
+                        c.cq_off = cqix(a, b, J);
+                        int terms = 0;
+                        for (int q = 0; q <= J / 2; ++q)
+                            for (int q1 = 0; q1 <= a; ++q1) {
+                                const int q2 = q - q1 + c.d;
+                                if (q2 >= 0 && q2 <= b) ++terms;
+                            }
+                        const int rowsn = c.p1hi - c.p1lo + 1;
+                        c.cost = rowsn * (6 * terms + 2 * (a + b + 2) + 4 * (J / 2 + 1)) + 16;
+                        t.yterms += (long)rowsn * terms;
+                        t.ypartials += (long)rowsn * (J / 2 + 1);
+                        pr.cs.push_back(c);
+                    }
+                // longest-processing-time assignment to the waves
+                std::stable_sort(pr.cs.begin(), pr.cs.end(),
+                                 [](const YContrib &x, const YContrib &y) { return x.cost > y.cost; });
+                std::vector<int> load(kYWaves, 0);
+                std::vector<std::vector<YContrib>> wav(kYWaves);
+                for (const auto &c : pr.cs) {
+                    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                    wav[w].push_back(c);
+                    load[w] += c.cost;
+                }
+                pr.cs.clear();
+                for (int w = 0; w < kYWaves; ++w) {
+                    pr.row.cb[w] = (int)pr.cs.size();
+                    pr.cs.insert(pr.cs.end(), wav[w].begin(), wav[w].end());
+                }
+                pr.row.cb[kYWaves] = (int)pr.cs.size();
+                pr.row.cost = *std::max_element(load.begin(), load.end());
+                rows.push_back(std::move(pr));
             }
-            for (int w = 0; w < kYWaves; ++w)
-                for (int x : wav[w]) pr.order.push_back(x);
-            int acc = 0;
-            for (int w = 0; w < kYWaves; ++w) {
-                pr.row.wb[w] = acc;
-                acc += (int)wav[w].size();
-            }
-            pr.row.wb[kYWaves] = acc;
-            pr.row.cost = *std::max_element(load.begin(), load.end());
-            pend.push_back(std::move(pr));
+        std::stable_sort(rows.begin(), rows.end(),
+                         [](const PendingC &x, const PendingC &y) { return x.row.cost > y.row.cost; });
+        for (auto &pr : rows) {
+            const int base = (int)t.ycontrib.size();
+            for (int w = 0; w <= kYWaves; ++w) pr.row.cb[w] += base;
+            t.ycontrib.insert(t.ycontrib.end(), pr.cs.begin(), pr.cs.end());
+            t.yrows.push_back(pr.row);
         }
-
-    // rows in decreasing cost so the heaviest start first
-    std::stable_sort(pend.begin(), pend.end(),
-                     [](const PendingRow &x, const PendingRow &y) { return x.row.cost > y.row.cost; });
-    for (auto &pr : pend) {
-        const int ib = (int)t.items.size();
-        for (int w = 0; w <= kYWaves; ++w) pr.row.wb[w] += ib;
-        for (int x : pr.order) {
-            ZItem it = pr.items[x];
-            const int tb0 = (int)t.terms.size();
-            for (int k = 0; k <= 4; ++k) it.tb[k] += tb0;
-            t.terms.insert(t.terms.end(), pr.terms[x].begin(), pr.terms[x].end());
-            t.items.push_back(it);
-        }
-        t.rows.push_back(pr.row);
     }
 
-    // bispectrum program: for each canonical (J1, J2, J), the items of
-    // Z^J_{J1 J2} over all stored (p, q), with the half-sum weight
-    std::vector<std::vector<BItem>> per_l(t.nb);
-    for (const auto &row : t.rows)
-        for (int x = row.wb[0]; x < row.wb[kYWaves]; ++x) {
-            const ZItem &it = t.items[x];
-            if (it.j1 > row.J || it.j2 > it.j1) continue;  // canonical: J >= J1 >= J2
-            const int l = cix(it.j1, it.j2, row.J);
-            if (l < 0) continue;
-            const int e = t.half_index(row.J, row.p, it.q);
-            per_l[l].push_back({x, e});
-        }
+    // bispectrum program (eq. (z)): for each canonical (J1, J2, J) and each
+    // stored (p, q) of rank J, the Clebsch-Gordan terms of Z(p, q)
     t.bl_begin.assign(t.nb + 1, 0);
     for (int l = 0; l < t.nb; ++l) {
-        t.bl_begin[l + 1] = t.bl_begin[l] + (int)per_l[l].size();
-        t.bitems.insert(t.bitems.end(), per_l[l].begin(), per_l[l].end());
+        const int J1 = t.comps[l][0], J2 = t.comps[l][1], J = t.comps[l][2];
+        for (int q = 0; q <= J / 2; ++q)
+            for (int p = 0; p <= J; ++p) {
+                BItem bi{};
+                bi.tb = (int)t.bterms.size();
+                const int M = 2 * p - J, Mq = 2 * q - J;
+                for (int p1 = 0; p1 <= J1; ++p1) {
+                    const int M1 = 2 * p1 - J1, M2 = M - M1;
+                    if (std::abs(M2) > J2) continue;
+                    const double cp = cg(J1, M1, J2, M2, J);
+                    if (std::fabs(cp) < 1e-15) continue;
+                    for (int q1 = 0; q1 <= J1; ++q1) {
+                        const int N1 = 2 * q1 - J1, N2 = Mq - N1;
+                        if (std::abs(N2) > J2) continue;
+                        const double cq = cg(J1, N1, J2, N2, J);
+                        if (std::fabs(cq) < 1e-15) continue;
+                        t.bterms.push_back({cp * cq, t.full_index(J1, p1, q1),
+                                            t.full_index(J2, (M2 + J2) / 2, (N2 + J2) / 2)});
+                    }
+                }
+                bi.te = (int)t.bterms.size();
+                bi.f3 = t.full_index(J, p, q);
+                bi.w = (2 * q < J) ? 2.0 : 1.0;
+                t.bitems.push_back(bi);
+            }
+        t.bl_begin[l + 1] = (int)t.bitems.size();
     }
 }
 

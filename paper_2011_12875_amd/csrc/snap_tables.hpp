@@ -16,51 +16,64 @@
 
 namespace snapmi {
 
-// Storage scaling.  The device keeps U and Y in scaled form,
-//   U~_e = U_e / N_e,   Y~_e = w_e N_e Y_e,
+// Storage.  compute_U writes U as full (J+1)x(J+1) matrices of true values,
+// element-major ("full index" f = fbase(J) + p (J+1) + q); the row loads of
+// compute_Y read it directly.  Y is kept on the stored half only, scaled:
+//   Y~_e = w_e N_e Y_e,
 // with N_e = sqrt(p!(J-p)!/(q!(J-q)!)) the normalisation of the polynomial
-// basis and w_e the half-sum weight (2 for q < J/2, 1 for q == J/2).  Then
-// the per-pair recursion runs on plain polynomial coefficients (no square
-// roots), Re(Y : conj(dU)) over the full matrix is a plain sum of
-// Re(Y~ conj(dpoly)) over the stored half, and N, w fold into the
-// Clebsch-Gordan coefficients of the contraction program.
-//
-// One term of a Clebsch-Gordan contraction:
-//   Z~(p, q) += cc * X(i1) * X(i2)
-// where X(i) is the stored (scaled) half element i, conjugated when the
-// operand falls in the unstored half; its sign, both operand
-// normalisations and the output scaling w N are folded into cc.
-struct Term {
-    double cc;
-    int32_t i1;
-    int32_t i2;
+// basis and w_e the half-sum weight (2 for q < J/2, 1 for q == J/2), so that
+// compute_dE contracts it with plain polynomial coefficients (no square
+// roots) and Re(Y : conj(dU)) over the full matrix is a plain sum over the
+// stored half.
+
+// Where compute_U puts a stored-half element e = (J, p, q): its full index
+// and that of its mirror (J, J-p, J-q) (-1 when e is its own mirror), with
+//   U(J-p, J-q) = (-1)^(p-q) conj(U(p, q))   and   U = N * poly-sum.
+struct UInfo {
+    int32_t fi, fm;
+    double nrm;    // N_e
+    double msign;  // (-1)^(p-q)
 };
 
-// One Z element Z^J_{J1 J2}(p, q) of the adjoint sum of eq. (y):
-// Y^J(p, q) += factor * beta[l] * Z.  Its terms are split by conjugation
-// pattern (bit 0: first operand conjugated, bit 1: second operand).
-struct ZItem {
-    int32_t q;        // output column (row and J come from the owning row)
-    int32_t l;        // canonical component whose coefficient weights it
-    double factor;    // multiplicity * (J_max + 1)/(J + 1)
-    int32_t tb[5];    // terms of pattern k are tb[k] .. tb[k+1]-1
-    int32_t j1, j2;   // input ranks (for inspection)
-};
-
-// A row (J, p) of Y, split over the waves of one workgroup.
+// Bispectrum program (eq. (z)): for a canonical l = (J1, J2, J),
+//   B_l = sum over stored (p, q) of w Re(Z(p, q) conj(U^J(p, q))),
+//   Z(p, q) = sum of terms cc U(f1) U(f2)   (full indices, true values).
 constexpr int kYWaves = 4;
-struct YRow {
-    int32_t J, p, nq, ebase;     // ebase: half index of (J, p, 0); stride J+1 per q
-    int32_t wb[kYWaves + 1];     // items of wave w: wb[w] .. wb[w+1]-1
-    int32_t cost;                // terms of the busiest wave
+struct BTerm {
+    double cc;
+    int32_t f1, f2;
+};
+struct BItem {
+    int32_t tb, te;  // terms tb .. te-1
+    int32_t f3;      // full index of U^J(p, q)
+    int32_t pad;
+    double w;        // half-sum weight
+};
+
+// Row-blocked form of the same contraction, used by compute_Y.  One
+// contribution is one input pair (J1 >= J2) of a row (J, p) of Y:
+//   Z(p, q) = sum_{p1} cp[p1] sum_{q1} cq[q][q1] U^J1(p1, q1) U^J2(p2, q2),
+//   p2 = p - p1 + d, q2 = q - q1 + d, d = (J1 + J2 - J)/2,
+// with true (unscaled) U values; cp and cq are Clebsch-Gordan coefficients.
+struct YContrib {
+    int32_t j1, j2, d, l;  // input ranks, offset d, canonical component l
+    double factor;         // multiplicity * (J_max + 1)/(J + 1)
+    int32_t p1lo, p1hi;    // rows p1 of U^J1 with a valid p2 (inclusive)
+    int32_t cp_off;        // cp of p1 at cp_off + (p1 - p1lo)
+    int32_t cq_off;        // cq[q][q1] at cq_off + q * (j1 + 1) + q1, q < nq
+    int32_t cost;          // estimated lane operations
     int32_t pad;
 };
 
-// One canonical component for the bispectrum kernel:
-// B_l = sum over its items of Re(Z~ * conj(U~^J(p, q)))  (= w N Z U*/N).
-struct BItem {
-    int32_t item;    // index into the Z items
-    int32_t e;       // half index of U^J(p, q)
+// A row (J, p) of Y in the row-blocked program, split over the waves of one
+// workgroup: contributions of wave w are cb[w] .. cb[w+1]-1.
+struct YRowC {
+    int32_t J, p, nq, ebase;
+    int32_t cb[kYWaves + 1];
+    int32_t cost;            // busiest wave
+    int32_t frow;            // full index of (J, p, 0)
+    double oscale[8];        // w N of the outputs (J, p, q): Y~ = w N Y
+    double einv[8];          // 1/N of the outputs: Re(Y~ conj(U)) / N = w Re(Y conj(U))
 };
 
 struct Tables {
@@ -69,20 +82,30 @@ struct Tables {
     int nb = 0;
     std::vector<int> hbase;                  // [twojmax+2] first half index of each J
     std::vector<std::array<int, 3>> helem;   // (J, p, q) per half index
+    int nfullel = 0;                         // sum (J+1)^2
     std::vector<double> norm;                // N_e per half index
     std::vector<double> whalf;               // 2 or 1 per half index
-    std::vector<double> unscale_u, unscale_y;// N_e and 1/(w_e N_e): scaled -> true values
+    std::vector<double> unscale_y;           // 1/(w_e N_e): Y~ -> Y
+    std::vector<int> half2full;              // full index of each half element
+    std::vector<UInfo> uinfo;
     std::vector<std::array<int, 3>> comps;   // canonical (J1, J2, J)
-    std::vector<Term> terms;
-    std::vector<ZItem> items;
-    std::vector<YRow> rows;                  // sorted by decreasing cost
+    std::vector<BTerm> bterms;
     std::vector<int> bl_begin;               // [nb+1] into bitems
     std::vector<BItem> bitems;
+    // row-blocked compute_Y program
+    std::vector<YContrib> ycontrib;
+    std::vector<YRowC> yrows;               // sorted by decreasing cost
+    std::vector<double> ycp, ycq;           // Clebsch-Gordan coefficient tables
+    long yterms = 0;                         // Clebsch-Gordan products per atom
+    long ypartials = 0;                      // (contribution, p1, q) partial sums per atom
+    std::vector<double> nfull;              // N of every full element, blocks of (J+1)^2
     // Clebsch-Gordan values actually used (for inspection and tests)
     std::vector<std::array<int, 5>> cg_keys; // J1, J2, J, M1, M2
     std::vector<double> cg_vals;
 
     int half_index(int J, int p, int q) const { return hbase[J] + q * (J + 1) + p; }
+    int full_index(int J, int p, int q) const { return fbase[J] + p * (J + 1) + q; }
+    std::vector<int> fbase;                  // [twojmax+2] first full index of each J
 };
 
 // Clebsch-Gordan coefficient <j1 m1 j2 m2 | j m>, arguments doubled,

@@ -180,7 +180,8 @@ class SnapPotential:
         return buf
 
     def program_size(self):
-        """(Clebsch-Gordan terms, Z items, Y rows) of the contraction program."""
+        """compute_Y work per atom: (Clebsch-Gordan products, partial sums,
+        contributions, rows)."""
         return tuple(int(x) for x in self.table(4))
 
     STAGES = ("compute_U", "compute_Y", "compute_dE", "update_forces", "bispectrum")
