@@ -157,6 +157,8 @@ class SnapPotential:
         self.rcut = float(rcut)
         self.ncoeff = lib.snap_ncoeff(ctx)
         self.nhalf = lib.snap_nhalf(ctx)
+        # counts snap_forward calls: backward() uses the U of the last one
+        self._fwd_token = 0
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
@@ -238,6 +240,7 @@ class SnapPotential:
             self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(out["energy"]),
             self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
             self._stream()))
+        self._fwd_token += 1  # U of this call replaces that of the last forward
         return out
 
     def forward(self, pos, box, nl, beta):
@@ -250,6 +253,7 @@ class SnapPotential:
             self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
             self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(E), self._ptr(B),
             self._stream()))
+        self._fwd_token += 1
         return E, B
 
     def backward(self, pos, box, nl, beta, grad_energy):
