@@ -125,6 +125,84 @@ def cpu_baseline(pos, box, beta, twojmax, budget_s=12.0):
                       "the oracle's O(N^2) neighbour search)" % (reps, n, dt)}
 
 
+def surrogate_leg(epochs, steps, warmup, log=None):
+    """Train the surrogate on the 10^4 seeded 250-atom configurations (labels
+    from 2J = 8 SNAP, descriptors and Jacobians from 2J = 4), judge it against
+    plain 2J = 8 SNAP on the 16000-atom configuration, and time both on it.
+    The speedup is t(plain 2J = 8 E+F) / t(surrogate E+F, including the 2J = 4
+    descriptors and the range gate, read back every step)."""
+    import numpy as np
+    import torch
+    from paper_2011_12875_amd import snapmi
+    from paper_2011_12875_amd import surrogate as sg
+    from paper_2011_12875_amd import workloads as wl
+
+    t0 = time.perf_counter()
+    pot4 = snapmi.SnapPotential(4, wl.RCUT, wl.RFAC0, wl.RMIN0, 1)
+    pot8 = snapmi.SnapPotential(8, wl.RCUT, wl.RFAC0, wl.RMIN0, 1)
+    beta8 = wl.surrogate_target_beta()
+    tr, va, te = wl.surrogate_split()
+    dtr = sg.make_surrogate_data(tr, pot8, beta8, pot4)
+    dva = sg.make_surrogate_data(va, pot8, beta8, pot4)
+    dte = sg.make_surrogate_data(te, pot8, beta8, pot4)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, hist = sg.train(dtr, sg.TrainConfig(epochs=epochs), dva, log=log)
+    t_train = time.perf_counter() - t0
+    test = sg.evaluate(net, dte)
+    lin = sg.evaluate_linear(*sg.fit_linear(dtr), dte)
+    ref_rms = float(dte.F.pow(2).mean().sqrt())
+    del dtr, dva, dte
+
+    pos, box = wl.surrogate_inference_config()
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    tpos = torch.as_tensor(pos, device="cuda")
+    sp = sg.SurrogatePotential(net, pot4, pot8, beta8)
+    judge = sp.judge(tpos, box, nl)
+    tb8 = torch.as_tensor(beta8, device="cuda")
+    n = len(pos)
+    out8 = {"energy": torch.empty(n, dtype=torch.float64, device="cuda"),
+            "force": torch.empty((n, 3), dtype=torch.float64, device="cuda")}
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / steps
+
+    ms_plain = timed(lambda: pot8.compute(tpos, box, nl, tb8, out=out8))
+    ms_sur = timed(lambda: sp.compute(tpos, box, nl, check=True))
+    ms_sur_nocheck = timed(lambda: sp.compute(tpos, box, nl, check=False))
+    pos_o, box_o = wl.surrogate_inference_config(ood=True)
+    nl_o = snapmi.NeighborList.build(pos_o, box_o, wl.RCUT)
+    ood = sp.compute(torch.as_tensor(pos_o, device="cuda"), box_o, nl_o)
+    rmse_mev = judge["force_rmse"] * 1e3
+    return {
+        "speedup": ms_plain / ms_sur,
+        "speedup_without_gate_readback": ms_plain / ms_sur_nocheck,
+        "ms_plain_2j8": ms_plain, "ms_surrogate": ms_sur,
+        "atoms": n, "force_rmse_meV_per_A": rmse_mev,
+        "meets_30meV_per_A": bool(rmse_mev <= 30.0),
+        "ref_force_rms_eV_per_A": judge["ref_force_rms"],
+        "force_max_err_eV_per_A": judge["force_max_err"],
+        "energy_rmse_eV_per_atom": judge["energy_rmse_per_atom"],
+        "fallback_on_inference_config": judge["fallback"],
+        "fallback_on_ood_config": bool(ood["fallback"]),
+        "test_set": {"force_rmse": test["force_rmse"], "energy_rmse": test["energy_rmse"],
+                     "ref_force_rms": ref_rms, "linear_2j4_force_rmse": lin["force_rmse"],
+                     "linear_2j4_energy_rmse": lin["energy_rmse"]},
+        "train": {"configs": len(tr), "epochs": epochs, "seconds": t_train,
+                  "data_seconds": t_data, "val_history": hist},
+        "target": "2J=8 SNAP, beta* ~ N(0, 0.1^2) x %.1f^((J-4)/2) above J=4 (seed %d)"
+                  % (wl.SURROGATE["target_decay"], wl.SURROGATE["target_seed"]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +211,8 @@ def main():
     ap.add_argument("--workload", default="bcc2000_2j8")
     ap.add_argument("--dedr-dirs", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-epochs", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device 3 times (a kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -212,6 +292,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(pos, box, beta, tj)
+    if not args.no_surrogate:
+        res["surrogate"] = surrogate_leg(args.surrogate_epochs, args.steps, args.warmup,
+                                         log=lambda r: print("surrogate", json.dumps(r),
+                                                             file=sys.stderr, flush=True))
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")

@@ -181,6 +181,99 @@ int snap_sync_status(snap_ctx *c, void *stream);
 /* Message of the last failing call on this thread ("" if none). */
 const char *snap_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate on cheap descriptors
+ *
+ * Eq. (snapatomenergy) is linear in the bispectrum; Sec. IV obtains forces
+ * from per-atom coefficients through the adjoint Y of eq. (y), and that route
+ * takes any per-atom coefficient vector.  The surrogate replaces beta . B_i by
+ * a small network of B_i computed at a low twojmax, E_i = f(x_i) with
+ * x_i = (B_i - mean) * scale, and gets its forces from the same adjoint with
+ * coefficients g_i = dE_i/dB_i (snap_backward with beta = g,
+ * per_atom_beta = 1 and grad_energy = 1).
+ *
+ * Network: nin -> 64 -> 64 -> 1, SiLU (silu(h) = h / (1 + exp(-h))) after
+ * both hidden layers, FP32 weights and FP32 accumulation; nin = 5, 14 or 30
+ * (N_B at 2J = 2, 4, 6).  params is one float array, row-major:
+ * W1[64][nin], b1[64], W2[64][64], b2[64], w3[64], b3 (snap_mlp_nparams
+ * floats).  norm is float[2][nin]: mean, then scale (1 / standard deviation).
+ * All pointers below are dev unless marked host; calls enqueue on stream and
+ * return without waiting.
+ * ------------------------------------------------------------------------ */
+
+/* Parameter count of the network for nin inputs (5185 for nin = 14), or
+ * SNAP_EINVAL for an unsupported nin. */
+int snap_mlp_nparams(int nin);
+
+/* Floats of workspace snap_mlp_grad needs for n atoms (< 0 on bad input). */
+long long snap_mlp_workspace(int nin, int n);
+
+/* Energies and input gradients of the network.
+ *   bispec  double[n][nin]   B_i
+ *   energy  double[n]        E_i = f(x_i)
+ *   grad_b  double[n][nin]   g_i = dE_i/dB_i
+ *   bounds  float[2][nin] or NULL: per input, the low and high end of the
+ *           range seen in training, in standardised units.  If any x_i,k lies
+ *           outside [lo - margin (hi - lo), hi + margin (hi - lo)] or is not
+ *           finite, *ood_flag is set to 1 (it is never cleared here).
+ *   ood_flag int[1] or NULL.
+ * Errors: SNAP_EINVAL, SNAP_EDEV. */
+int snap_mlp_forward(int nin, int n, const float *params, const float *norm,
+                     const float *bounds, float margin, const double *bispec, double *energy,
+                     double *grad_b, int *ood_flag, void *stream);
+
+/* Parameter gradient of  Phi = sum_i dl_de_i E_i + dl_dg_i . g_i  (grad,
+ * float[nparams], overwritten): back-propagation for the first term,
+ * forward-over-reverse differentiation for the second, so that a loss on
+ * energies and on forces (through dl_dg, see snap_jacobian_adjoint) is
+ * differentiated exactly.  dl_de double[n]; dl_dg double[n][nin] or NULL;
+ * work float[snap_mlp_workspace(nin, n)].  Per-block partial sums are added in
+ * a fixed order: the result is deterministic.  Errors: SNAP_EINVAL, SNAP_EDEV. */
+int snap_mlp_grad(int nin, int n, const float *params, const float *norm, const double *bispec,
+                  const double *dl_de, const double *dl_dg, float *work, float *grad,
+                  void *stream);
+
+/* One Adam step (Kingma and Ba, 2015) on np parameters: m and v (float[np],
+ * zero before step 1) are the moment estimates, step >= 1 the step number for
+ * the bias corrections 1 - beta^step.  Errors: SNAP_EINVAL, SNAP_EDEV. */
+int snap_adam_step(int np, float *params, float *m, float *v, const float *grad, float lr,
+                   float beta1, float beta2, float eps, int step, void *stream);
+
+/* Descriptor Jacobian: the bispectrum B_i (eq. (z)) and, per pair
+ * p = (i -> k), J_p = dB_i/dr_ik (eq. (dbidrk), kept per neighbour as the
+ * compute_dB stage of Sec. II.B does, here obtained from the adjoint stages
+ * with one unit coefficient vector per component: compute_Y with beta = e_l,
+ * then compute_dE).
+ *   bispec double[n][N_B] or NULL;  jac float[npairs][N_B][3].
+ * Other arguments as in snap_compute.  Keeps U_j like snap_forward. */
+int snap_jacobian(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                  const int *off, const int *nbr, const int *rev, double *bispec, float *jac,
+                  void *stream);
+
+/* Forces of per-atom energies with input gradients g_i from a stored
+ * Jacobian: dE_p = J_p^T g_i per pair (dE_pair double[npairs][3], written),
+ * then update_forces as in snap_compute (force double[n][3]).  off, rev as in
+ * snap_compute; jac float[npairs][nin][3]; grad_b double[n][nin]. */
+int snap_jacobian_forces(int nin, int n, int npairs, const int *off, const int *rev,
+                         const float *jac, const double *grad_b, double *dE_pair, double *force,
+                         void *stream);
+
+/* Reverse of snap_jacobian_forces: for dl_dforce = dL/dF (double[n][3]),
+ * dl_dg_i = sum over pairs p = (i -> k) of J_p (dl_dforce_i - dl_dforce_k)
+ * (double[n][nin]). */
+int snap_jacobian_adjoint(int nin, int n, int npairs, const int *off, const int *nbr,
+                          const float *jac, const double *dl_dforce, double *dl_dg, void *stream);
+
+/* Residuals of the loss L = w_energy sum_i (E_i - Eref_i)^2
+ *                          + w_force sum_i |F_i - Fref_i|^2:
+ * dl_de double[n] = 2 w_energy (E - Eref), dl_dforce double[n][3] =
+ * 2 w_force (F - Fref), and sums double[ceil(n/256)][2], per block of 256
+ * atoms, of (E - Eref)^2 and |F - Fref|^2. */
+int snap_fit_residuals(int n, const double *energy, const double *energy_ref,
+                       const double *force, const double *force_ref, double w_energy,
+                       double w_force, double *dl_de, double *dl_dforce, double *sums,
+                       void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,11 +24,12 @@ UNITS = [
     ("snap_dedr.hip", ["-DSNAP_DEDR_LOW"], "snap_dedr_low.o"),
     ("snap_dedr.hip", [], "snap_dedr_high.o"),
     ("snap_misc.hip", [], "snap_misc.o"),
+    ("snap_mlp.hip", [], "snap_mlp.o"),
 ]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    # packed FP32 instructions stay off (the kernels are FP64)
+    # packed FP32 instructions stay off
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]

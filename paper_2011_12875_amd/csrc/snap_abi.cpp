@@ -115,6 +115,7 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(d.ycp);
     (void)hipFree(d.ycq);
     (void)hipFree(d.nfull);
+    (void)hipFree(d.onehot);
     d = DevTables();
     Work &w = c->work;
     (void)hipFree(w.U);
@@ -151,6 +152,11 @@ static int ensure_device(snap_ctx *c)
     HIP_TRY(upload(d.ycp, t.ycp), "upload ycp");
     HIP_TRY(upload(d.ycq, t.ycq), "upload ycq");
     HIP_TRY(upload(d.nfull, t.nfull), "upload nfull");
+    {
+        std::vector<double> eye((size_t)t.nb * t.nb, 0.0);
+        for (int l = 0; l < t.nb; ++l) eye[(size_t)l * t.nb + l] = 1.0;
+        HIP_TRY(upload(d.onehot, eye), "upload unit coefficient vectors");
+    }
     d.nyrows = (int)t.yrows.size();
     HIP_TRY(hipMalloc((void **)&c->work.flag, sizeof(int)), "alloc flag");
     HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
@@ -384,14 +390,16 @@ int snap_check_neighbors(int n, const int *off, const int *nbr, const int *rev, 
 }
 
 static int common_checks(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
-                         const int *off, const int *nbr, const int *rev, const double *beta)
+                         const int *off, const int *nbr, const int *rev, const double *beta,
+                         bool need_beta = true)
 {
     if (!c) return fail(SNAP_EINVAL, "NULL context");
     if (n < 0 || npairs < 0) return fail(SNAP_EINVAL, "negative size");
     if (n > (1 << 24) || npairs > (1 << 30)) return fail(SNAP_EINVAL, "size too large");
     int st = check_box(box, c->prm.rcut);
     if (st) return st;
-    if (n > 0 && (!pos || !off || !beta)) return fail(SNAP_EINVAL, "NULL input pointer");
+    if (n > 0 && (!pos || !off || (need_beta && !beta)))
+        return fail(SNAP_EINVAL, "NULL input pointer");
     if (npairs > 0 && (!nbr || !rev)) return fail(SNAP_EINVAL, "NULL neighbour pointer");
     return SNAP_OK;
 }
@@ -560,6 +568,179 @@ int snap_sync_status(snap_ctx *c, void *stream)
         HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
         return fail(SNAP_EGEOM, "coincident atoms (r < 1e-10 A) or non-finite positions");
     }
+    return SNAP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// learned surrogate
+// ---------------------------------------------------------------------------
+
+int snap_jacobian(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                  const int *off, const int *nbr, const int *rev, double *bispec, float *jac,
+                  void *stream)
+{
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, nullptr, false);
+    if (st) return st;
+    if (npairs > 0 && !jac) return fail(SNAP_EINVAL, "NULL Jacobian pointer");
+    if ((st = ensure_device(c))) return st;
+    if (n == 0) return SNAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
+    const Geom g = make_geom(c, box);
+    Work &w = c->work;
+    const int nb = c->tab.nb;
+    if ((st = run_u(c, n, npairs, pos, g, off, nbr, s))) return st;
+    if (bispec)
+        HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, bispec, nullptr, 0, nullptr, s),
+                "bispectrum launch");
+    c->last_n = n;
+    if (npairs == 0) return SNAP_OK;
+    for (int l = 0; l < nb; ++l) {
+        const double *el = c->dev.onehot + (size_t)l * nb;
+        HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, el, 0, nb, nullptr,
+                                 nullptr, s),
+                "compute_Y launch");
+        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
+                            w.Y, c->dev, g, w.dE, s),
+                "compute_dE launch");
+        HIP_TRY(launch_pack_jac(npairs, nb, l, w.dE, jac, s), "Jacobian store");
+    }
+    return SNAP_OK;
+}
+
+// Checks shared by the context-free entry points: a usable gfx950 device.
+static int check_free_call(int nin)
+{
+    if (nin >= 0 && !mlp_supported(nin)) return fail(SNAP_EINVAL, "nin %d not supported (5, 14, 30)", nin);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    static thread_local int checked_dev = -1;
+    if (checked_dev != dev) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(SNAP_EDEV, "device %d is %s; this library is built for gfx950", dev,
+                        prop.gcnArchName);
+        checked_dev = dev;
+    }
+    return SNAP_OK;
+}
+
+int snap_mlp_nparams(int nin)
+{
+    if (!mlp_supported(nin)) return fail(SNAP_EINVAL, "nin %d not supported (5, 14, 30)", nin);
+    return mlp_nparams(nin);
+}
+
+long long snap_mlp_workspace(int nin, int n)
+{
+    if (!mlp_supported(nin)) return fail(SNAP_EINVAL, "nin %d not supported (5, 14, 30)", nin);
+    if (n < 0 || n > (1 << 24)) return fail(SNAP_EINVAL, "n out of range");
+    return (long long)mlp_grad_workspace(nin, n);
+}
+
+int snap_mlp_forward(int nin, int n, const float *params, const float *norm,
+                     const float *bounds, float margin, const double *bispec, double *energy,
+                     double *grad_b, int *ood_flag, void *stream)
+{
+    if (n < 0 || n > (1 << 24)) return fail(SNAP_EINVAL, "n out of range");
+    if (!std::isfinite(margin) || margin < 0.0f) return fail(SNAP_EINVAL, "margin must be >= 0");
+    int st = check_free_call(nin);
+    if (st) return st;
+    if (n == 0) return SNAP_OK;
+    if (!params || !norm || !bispec || !energy || !grad_b)
+        return fail(SNAP_EINVAL, "NULL pointer argument");
+    HIP_TRY(launch_mlp_forward(nin, n, params, norm, bounds, margin, bispec, energy, grad_b,
+                               ood_flag, (hipStream_t)stream),
+            "network forward launch");
+    return SNAP_OK;
+}
+
+int snap_mlp_grad(int nin, int n, const float *params, const float *norm, const double *bispec,
+                  const double *dl_de, const double *dl_dg, float *work, float *grad,
+                  void *stream)
+{
+    if (n < 0 || n > (1 << 24)) return fail(SNAP_EINVAL, "n out of range");
+    int st = check_free_call(nin);
+    if (st) return st;
+    if (!grad) return fail(SNAP_EINVAL, "NULL gradient pointer");
+    hipStream_t s = (hipStream_t)stream;
+    if (n > 0 && (!params || !norm || !bispec || !dl_de || !work))
+        return fail(SNAP_EINVAL, "NULL pointer argument");
+    HIP_TRY(launch_mlp_grad(nin, n, params, norm, bispec, dl_de, dl_dg, work, grad, s),
+            "network gradient launch");
+    return SNAP_OK;
+}
+
+int snap_adam_step(int np, float *params, float *m, float *v, const float *grad, float lr,
+                   float beta1, float beta2, float eps, int step, void *stream)
+{
+    if (np <= 0 || !params || !m || !v || !grad) return fail(SNAP_EINVAL, "bad Adam arguments");
+    if (step < 1) return fail(SNAP_EINVAL, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+        !std::isfinite(lr))
+        return fail(SNAP_EINVAL, "Adam hyper-parameters out of range");
+    int st = check_free_call(-1);
+    if (st) return st;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    HIP_TRY(launch_adam(np, params, m, v, grad, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream),
+            "Adam launch");
+    return SNAP_OK;
+}
+
+int snap_jacobian_forces(int nin, int n, int npairs, const int *off, const int *rev,
+                         const float *jac, const double *grad_b, double *dE_pair, double *force,
+                         void *stream)
+{
+    if (n < 0 || npairs < 0 || n > (1 << 24) || npairs > (1 << 30))
+        return fail(SNAP_EINVAL, "size out of range");
+    int st = check_free_call(nin);
+    if (st) return st;
+    if (n == 0) return SNAP_OK;
+    if (!off || !grad_b || !force || (npairs > 0 && (!rev || !jac || !dE_pair)))
+        return fail(SNAP_EINVAL, "NULL pointer argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (npairs > 0)
+        HIP_TRY(launch_jac_force(nin, n, npairs, off, jac, grad_b, dE_pair, s),
+                "Jacobian force launch");
+    HIP_TRY(launch_gather(n, 0, 0, off, rev, dE_pair, nullptr, nullptr, force, s),
+            "update_forces launch");
+    return SNAP_OK;
+}
+
+int snap_jacobian_adjoint(int nin, int n, int npairs, const int *off, const int *nbr,
+                          const float *jac, const double *dl_dforce, double *dl_dg, void *stream)
+{
+    if (n < 0 || npairs < 0 || n > (1 << 24) || npairs > (1 << 30))
+        return fail(SNAP_EINVAL, "size out of range");
+    int st = check_free_call(nin);
+    if (st) return st;
+    if (n == 0) return SNAP_OK;
+    if (!off || !dl_dforce || !dl_dg || (npairs > 0 && (!nbr || !jac)))
+        return fail(SNAP_EINVAL, "NULL pointer argument");
+    HIP_TRY(launch_jac_adjoint(nin, n, off, nbr, jac, dl_dforce, dl_dg, (hipStream_t)stream),
+            "Jacobian adjoint launch");
+    return SNAP_OK;
+}
+
+int snap_fit_residuals(int n, const double *energy, const double *energy_ref,
+                       const double *force, const double *force_ref, double w_energy,
+                       double w_force, double *dl_de, double *dl_dforce, double *sums,
+                       void *stream)
+{
+    if (n < 0 || n > (1 << 24)) return fail(SNAP_EINVAL, "n out of range");
+    if (!std::isfinite(w_energy) || !std::isfinite(w_force))
+        return fail(SNAP_EINVAL, "loss weights must be finite");
+    int st = check_free_call(-1);
+    if (st) return st;
+    if (n == 0) return SNAP_OK;
+    if (!energy || !energy_ref || !force || !force_ref || !dl_de || !dl_dforce || !sums)
+        return fail(SNAP_EINVAL, "NULL pointer argument");
+    HIP_TRY(launch_residuals(n, energy, energy_ref, force, force_ref, w_energy, w_force, dl_de,
+                             dl_dforce, sums, (hipStream_t)stream),
+            "residual launch");
     return SNAP_OK;
 }
 

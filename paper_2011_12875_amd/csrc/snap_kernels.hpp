@@ -24,6 +24,7 @@ struct DevTables {
     YContrib *ycontrib = nullptr;
     YRowC *yrows = nullptr;
     double *ycp = nullptr, *ycq = nullptr, *nfull = nullptr;
+    double *onehot = nullptr;  // identity [nb][nb]: unit coefficient vectors
     int nyrows = 0;
 };
 
@@ -73,5 +74,33 @@ hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *
 // dst[e][atom][re/im] = scale[e] * src[map[e] * npad + atom] for atom < n
 hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const int *map,
                           const double *scale, double *dst, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// surrogate network and descriptor Jacobian (snap_mlp.hip)
+// ---------------------------------------------------------------------------
+constexpr int kMlpHidden = 64;     // width of both hidden layers
+constexpr int kMlpGradAtoms = 64;  // atoms per block of the parameter gradient
+
+bool mlp_supported(int nin);
+int mlp_nparams(int nin);
+// floats of workspace launch_mlp_grad needs for n atoms
+size_t mlp_grad_workspace(int nin, int n);
+
+hipError_t launch_mlp_forward(int nin, int n, const float *prm, const float *norm,
+                              const float *bounds, float margin, const double *B, double *E,
+                              double *g, int *flag, hipStream_t s);
+hipError_t launch_mlp_grad(int nin, int n, const float *prm, const float *norm, const double *B,
+                           const double *rE, const double *v, float *work, float *grad,
+                           hipStream_t s);
+hipError_t launch_adam(int np, float *prm, float *m, float *v, const float *grad, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_pack_jac(int npairs, int nb, int l, const double *dE, float *jac, hipStream_t s);
+hipError_t launch_jac_force(int nin, int n, int npairs, const int *off, const float *jac,
+                            const double *g, double *dE, hipStream_t s);
+hipError_t launch_jac_adjoint(int nin, int n, const int *off, const int *nbr, const float *jac,
+                              const double *lam, double *v, hipStream_t s);
+hipError_t launch_residuals(int n, const double *E, const double *Eref, const double *F,
+                            const double *Fref, double wE, double wF, double *rE, double *lam,
+                            double *sums, hipStream_t s);
 
 }  // namespace snapmi

@@ -24,7 +24,10 @@ ERRORS = {-1: "SNAP_EINVAL", -2: "SNAP_EBOX", -3: "SNAP_ENBR", -4: "SNAP_EGEOM",
 EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_nhalf",
            "snap_table", "snap_build_neighbors", "snap_check_neighbors", "snap_compute",
            "snap_forward", "snap_backward", "snap_copy_workspace", "snap_profile",
-           "snap_stage_times", "snap_sync_status", "snap_last_error"]
+           "snap_stage_times", "snap_sync_status", "snap_last_error",
+           "snap_mlp_nparams", "snap_mlp_workspace", "snap_mlp_forward", "snap_mlp_grad",
+           "snap_adam_step", "snap_jacobian", "snap_jacobian_forces", "snap_jacobian_adjoint",
+           "snap_fit_residuals"]
 
 
 class SnapError(RuntimeError):
@@ -51,7 +54,7 @@ def load():
         raise ImportError("libsnapmi.so is not built: run python -m paper_2011_12875_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
     vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
-    i, d = ctypes.c_int, ctypes.c_double
+    i, d, f = ctypes.c_int, ctypes.c_double, ctypes.c_float
     sig = {
         "snap_setup": (i, [i, d, d, d, i, ctypes.POINTER(vp)]),
         "snap_setup_ex": (i, [ctypes.POINTER(snap_params), ctypes.POINTER(vp)]),
@@ -69,6 +72,15 @@ def load():
         "snap_profile": (i, [vp, i]),
         "snap_stage_times": (i, [vp, dp, ip]),
         "snap_last_error": (ctypes.c_char_p, []),
+        "snap_mlp_nparams": (i, [i]),
+        "snap_mlp_workspace": (ctypes.c_longlong, [i, i]),
+        "snap_mlp_forward": (i, [i, i, vp, vp, vp, f, vp, vp, vp, vp, vp]),
+        "snap_mlp_grad": (i, [i, i, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "snap_adam_step": (i, [i, vp, vp, vp, vp, f, f, f, f, i, vp]),
+        "snap_jacobian": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp]),
+        "snap_jacobian_forces": (i, [i, i, i, vp, vp, vp, vp, vp, vp, vp]),
+        "snap_jacobian_adjoint": (i, [i, i, i, vp, vp, vp, vp, vp, vp]),
+        "snap_fit_residuals": (i, [i, vp, vp, vp, vp, d, d, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -256,18 +268,37 @@ class SnapPotential:
         self._fwd_token += 1
         return E, B
 
-    def backward(self, pos, box, nl, beta, grad_energy):
+    def backward(self, pos, box, nl, beta, grad_energy, force=None):
         """-d(sum_i g_i E_i)/dr (the forces of the weighted energy)."""
         import torch
         n, boxa, per_atom = self._args(pos, box, nl, beta)
         g = grad_energy.contiguous()
         assert g.dtype == torch.float64 and g.shape == (n,)
-        F = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        F = force if force is not None else torch.empty((n, 3), dtype=torch.float64,
+                                                        device=pos.device)
         _check(load().snap_backward(
             self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
             self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(g), self._ptr(F), None,
             self._stream()))
         return F
+
+    def jacobian(self, pos, box, nl, bispectrum=None, jac=None):
+        """B_i [n, N_B] (float64) and J_p = dB_i/dr_ik [P, N_B, 3] (float32)."""
+        import torch
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+        n = pos.shape[0]
+        assert nl.n == n
+        boxa = (ctypes.c_double * 3)(*[float(x) for x in box])
+        if bispectrum is None:
+            bispectrum = torch.empty((n, self.ncoeff), dtype=torch.float64, device=pos.device)
+        if jac is None:
+            jac = torch.empty((max(nl.npairs, 1), self.ncoeff, 3), dtype=torch.float32,
+                              device=pos.device)
+        _check(load().snap_jacobian(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(bispectrum), self._ptr(jac), self._stream()))
+        self._fwd_token += 1
+        return bispectrum, jac
 
     def workspace(self, which, n):
         """True U_j (which=0) or Y_j (which=1) of the last call: [nhalf, n] complex."""
@@ -278,3 +309,138 @@ class SnapPotential:
 
     def sync_status(self):
         return _check(load().snap_sync_status(self._ctx, self._stream()))
+
+
+# ---------------------------------------------------------------------------
+# learned surrogate: network, optimiser and descriptor-Jacobian kernels
+# ---------------------------------------------------------------------------
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape=None):
+    import torch
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.dtype, t.device)
+    if shape is not None:
+        assert tuple(t.shape) == tuple(shape), (tuple(t.shape), shape)
+    return t
+
+
+def mlp_nparams(nin):
+    n = load().snap_mlp_nparams(int(nin))
+    _check(0 if n >= 0 else n)
+    return n
+
+
+def mlp_workspace(nin, n):
+    k = load().snap_mlp_workspace(int(nin), int(n))
+    _check(0 if k >= 0 else int(k))
+    return int(k)
+
+
+def mlp_forward(params, norm, bispec, bounds=None, margin=0.0, flag=None, energy=None,
+                grad_b=None):
+    """(E_i, g_i = dE_i/dB_i) of the network; sets flag[0] = 1 on inputs
+    outside the bounds widened by margin."""
+    import torch
+    n, nin = bispec.shape
+    _dev(params, torch.float32, (mlp_nparams(nin),))
+    _dev(norm, torch.float32, (2, nin))
+    _dev(bispec, torch.float64)
+    if bounds is not None:
+        _dev(bounds, torch.float32, (2, nin))
+    if flag is not None:
+        _dev(flag, torch.int32)
+    E = energy if energy is not None else torch.empty(n, dtype=torch.float64, device=bispec.device)
+    g = grad_b if grad_b is not None else torch.empty((n, nin), dtype=torch.float64,
+                                                      device=bispec.device)
+    _check(load().snap_mlp_forward(nin, n, _p(params), _p(norm), _p(bounds), float(margin),
+                                   _p(bispec), _p(E), _p(g), _p(flag), _stream()))
+    return E, g
+
+
+def mlp_grad(params, norm, bispec, dl_de, dl_dg=None, work=None, grad=None):
+    """d/dtheta of sum_i dl_de_i E_i + dl_dg_i . g_i (float32 [nparams])."""
+    import torch
+    n, nin = bispec.shape
+    np_ = mlp_nparams(nin)
+    _dev(params, torch.float32, (np_,))
+    _dev(norm, torch.float32, (2, nin))
+    _dev(bispec, torch.float64)
+    _dev(dl_de, torch.float64, (n,))
+    if dl_dg is not None:
+        _dev(dl_dg, torch.float64, (n, nin))
+    need = mlp_workspace(nin, n)
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.float32, device=bispec.device)
+    assert work.numel() >= need
+    if grad is None:
+        grad = torch.empty(np_, dtype=torch.float32, device=bispec.device)
+    _check(load().snap_mlp_grad(nin, n, _p(params), _p(norm), _p(bispec), _p(dl_de), _p(dl_dg),
+                                _p(work), _p(grad), _stream()))
+    return grad
+
+
+def adam_step(params, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    import torch
+    np_ = params.numel()
+    for t in (params, m, v, grad):
+        _dev(t, torch.float32, (np_,))
+    _check(load().snap_adam_step(np_, _p(params), _p(m), _p(v), _p(grad), float(lr), float(beta1),
+                                 float(beta2), float(eps), int(step), _stream()))
+
+
+def jacobian_forces(nl, jac, grad_b, dE=None, force=None):
+    """Forces of per-atom energies with input gradients grad_b, from J_p."""
+    import torch
+    n, nin = grad_b.shape
+    assert nl.n == n
+    _dev(grad_b, torch.float64)
+    _dev(jac, torch.float32)
+    assert jac.shape[0] >= nl.npairs and jac.shape[1:] == (nin, 3)
+    if dE is None:
+        dE = torch.empty((max(nl.npairs, 1), 3), dtype=torch.float64, device=grad_b.device)
+    if force is None:
+        force = torch.empty((n, 3), dtype=torch.float64, device=grad_b.device)
+    _check(load().snap_jacobian_forces(nin, n, nl.npairs, _p(nl.off), _p(nl.rev), _p(jac),
+                                       _p(grad_b), _p(dE), _p(force), _stream()))
+    return force
+
+
+def jacobian_adjoint(nl, jac, dl_dforce, nin, out=None):
+    """dl_dg_i = sum_{p = (i -> k)} J_p (dl_dforce_i - dl_dforce_k)."""
+    import torch
+    n = nl.n
+    _dev(dl_dforce, torch.float64, (n, 3))
+    _dev(jac, torch.float32)
+    assert jac.shape[0] >= nl.npairs and jac.shape[1:] == (nin, 3)
+    if out is None:
+        out = torch.empty((n, nin), dtype=torch.float64, device=dl_dforce.device)
+    _check(load().snap_jacobian_adjoint(nin, n, nl.npairs, _p(nl.off), _p(nl.nbr), _p(jac),
+                                        _p(dl_dforce), _p(out), _stream()))
+    return out
+
+
+def fit_residuals(energy, energy_ref, force, force_ref, w_energy, w_force, dl_de=None,
+                  dl_dforce=None, sums=None):
+    """(dl_de, dl_dforce, sums[nblk, 2]) of the weighted squared-error loss."""
+    import torch
+    n = energy.shape[0]
+    for t, shp in ((energy, (n,)), (energy_ref, (n,)), (force, (n, 3)), (force_ref, (n, 3))):
+        _dev(t, torch.float64, shp)
+    dev = energy.device
+    if dl_de is None:
+        dl_de = torch.empty(n, dtype=torch.float64, device=dev)
+    if dl_dforce is None:
+        dl_dforce = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    if sums is None:
+        sums = torch.empty((max((n + 255) // 256, 1), 2), dtype=torch.float64, device=dev)
+    _check(load().snap_fit_residuals(n, _p(energy), _p(energy_ref), _p(force), _p(force_ref),
+                                     float(w_energy), float(w_force), _p(dl_de), _p(dl_dforce),
+                                     _p(sums), _stream()))
+    return dl_de, dl_dforce, sums

@@ -104,3 +104,77 @@ def make(name: str):
         pos, box = bcc(w["ncell"], w["sigma"], w["pos_seed"])
     b = beta(ncoeff(w["twojmax"]), w["beta_seed"])
     return pos, box, b, w["twojmax"]
+
+
+# ---------------------------------------------------------------------------
+# Learned surrogate: training configurations, target coefficients, inference
+# and out-of-range configurations.
+# ---------------------------------------------------------------------------
+SURROGATE = dict(
+    ncell_train=5,          # 250 atoms per configuration, L = 15.9015 A
+    n_configs=10000,
+    sigma_range=(0.02, 0.2),
+    config_seed0=10000,     # configuration c draws sigma_c and positions from seed 10000 + c
+    split_seed=11,
+    split=(8000, 1000, 1000),
+    target_seed=9,          # target coefficients of the 2J = 8 potential
+    target_decay=0.3,       # per unit of J above 4, in amplitude: decay ** ((J - 4) / 2)
+    model_twojmax=4,
+    label_twojmax=8,
+    ncell_infer=20, sigma_infer=0.1, infer_seed=12,   # 16000 atoms
+    sigma_ood=0.35, ood_seed=13,
+)
+
+
+def components(twojmax: int):
+    """(J1, J2, J) of each bispectrum component in the library's order
+    (counting only)."""
+    out = []
+    for j1 in range(twojmax + 1):
+        for j2 in range(j1 + 1):
+            for j in range(j1 - j2, min(twojmax, j1 + j2) + 1, 2):
+                if j >= j1:
+                    out.append((j1, j2, j))
+    return out
+
+
+def surrogate_config(c: int, ncell: int | None = None):
+    """Training configuration c: BCC of ncell^3 cells (5 by default) with
+    Gaussian displacements of a width sigma_c ~ U(sigma_range); sigma_c and
+    the displacements come from seed config_seed0 + c.  Returns (pos, box,
+    sigma_c)."""
+    s = SURROGATE
+    ncell = ncell or s["ncell_train"]
+    sites, box = bcc(ncell, 0.0, 0)
+    rng = np.random.default_rng(s["config_seed0"] + c)
+    sigma = rng.uniform(*s["sigma_range"])
+    pos = np.mod(sites + rng.normal(0.0, sigma, size=sites.shape), box[0])
+    return np.ascontiguousarray(pos), box, sigma
+
+
+def surrogate_split():
+    """(train, val, test) configuration indices."""
+    s = SURROGATE
+    perm = np.random.default_rng(s["split_seed"]).permutation(s["n_configs"])
+    a, b, _ = s["split"]
+    return perm[:a], perm[a:a + b], perm[a + b:]
+
+
+def surrogate_target_beta(decay: float | None = None):
+    """Target coefficients of the 2J = 8 potential: N(0, 0.1^2) draws from
+    target_seed, scaled by decay ** ((J - 4) / 2) for components whose J
+    exceeds 4 (decay = 1 leaves them undamped)."""
+    s = SURROGATE
+    decay = s["target_decay"] if decay is None else decay
+    b = beta(ncoeff(s["label_twojmax"]), s["target_seed"])
+    damp = np.array([decay ** (max(0, j - 4) / 2.0) for (_, _, j) in components(s["label_twojmax"])])
+    return b * damp
+
+
+def surrogate_inference_config(ood: bool = False):
+    """The 16000-atom inference configuration (sigma 0.1) or, with ood, the
+    out-of-range one (sigma 0.35)."""
+    s = SURROGATE
+    if ood:
+        return bcc(s["ncell_infer"], s["sigma_ood"], s["ood_seed"])
+    return bcc(s["ncell_infer"], s["sigma_infer"], s["infer_seed"])

@@ -24,7 +24,7 @@ def _lib():
 
 def test_header_symbols_are_exported():
     hdr = open(os.path.join(ROOT, "include", "snapmi.h")).read()
-    declared = set(re.findall(r"^(?:int|const char \*)\s*(snap_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^(?:int|long long|const char \*)\s*(snap_\w+)\s*\(", hdr, re.M))
     assert declared == set(snapmi.EXPORTS)
     lib = _lib()
     for name in declared:
