@@ -15,15 +15,30 @@ template <int TJ, int ND>
 struct DedrState {
     double2 col[TJ + 1], seed[TJ + 1];
     double2 dcol[ND][TJ + 1], dseed[ND][TJ + 1];
+    double2 y[TJ + 1];  // Y~ of the current level, loaded one level ahead
     double S0, S[ND];
 };
+
+// Y~ rows eb .. eb + J of the atom (the level's stored elements) into y.
+template <int TJ>
+__device__ __forceinline__ void load_level(double2 (&y)[TJ + 1], int J, int eb,
+                                           const double2 *__restrict__ Y, unsigned i, int npad)
+{
+#pragma unroll
+    for (int p = 0; p <= TJ; ++p)
+        if (p <= J) y[p] = load_row(Y, (size_t)(eb + p), npad, i * 16u);
+}
 
 // One level: recursion for poly and its derivatives, then the dot with Y~.
 // The top row p = J has no col[J] term; DZ marks a level whose input
 // derivatives are all zero (the first level of column 0, from poly^0 = 1).
+// The Y~ of the level is already in st.y; the loads of the next level
+// (size Jn + 1 at half index ebn, Jn < 0 for none) are issued before the
+// compiler fence that closes the level, so that their latency overlaps the
+// next level's recursion.
 template <int TJ, int ND, bool DZ>
-__device__ __forceinline__ void dedr_level(int J, int eb, DedrState<TJ, ND> &st, double2 a,
-                                           double2 b, const double2 (&da)[ND],
+__device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ, ND> &st,
+                                           double2 a, double2 b, const double2 (&da)[ND],
                                            const double2 (&db)[ND],
                                            const double2 *__restrict__ Y, unsigned i, int npad)
 {
@@ -71,11 +86,12 @@ __device__ __forceinline__ void dedr_level(int J, int eb, DedrState<TJ, ND> &st,
 #pragma unroll
     for (int p = 0; p <= TJ; ++p)
         if (p <= J) {
-            const double2 y = load_row(Y, (size_t)(eb + p), npad, i * 16u);
+            const double2 y = st.y[p];
             st.S0 += y.x * st.col[p].x + y.y * st.col[p].y;
 #pragma unroll
             for (int d = 0; d < ND; ++d) st.S[d] += y.x * st.dcol[d][p].x + y.y * st.dcol[d][p].y;
         }
+    if (Jn >= 0) load_level<TJ>(st.y, Jn, ebn, Y, i, npad);
 #pragma unroll
     for (int p = 0; p <= TJ; ++p)
         if (p <= J) {
@@ -102,20 +118,22 @@ __device__ __forceinline__ void dedr_column(DedrState<TJ, ND> &st, double2 a, do
         for (int d = 0; d < ND; ++d)
             st.dcol[d][p] = fromseed ? st.dseed[d][p] : make_double2(0.0, 0.0);
     }
-    if (Q == 0) {
-        st.col[0] = make_double2(1.0, 0.0);
-        st.S0 += load_row(Y, 0, npad, i * 16u).x;  // J = 0: poly = 1, dpoly = 0
-    }
+    if (Q == 0) st.col[0] = make_double2(1.0, 0.0);
     constexpr int J0 = (Q == 0) ? 1 : 2 * Q;
+    // the level after the last one of this column: the first of the next
+    constexpr int QN = Q + 1;
+    constexpr int JN = (2 * QN <= TJ) ? 2 * QN : -1;
+    constexpr int EBN = (JN >= 0) ? hbase_of(2 * QN) + QN * (2 * QN + 1) : 0;
     constexpr bool kFull = TJ <= 10;  // straight-line code up to 2J = 10
     if constexpr (kFull) {
 #pragma unroll
         for (int J = J0; J <= TJ; ++J) {
+            const int Jn = (J < TJ) ? J + 1 : JN;
+            const int ebn = (J < TJ) ? hbase_of(J + 1) + Q * (J + 2) : EBN;
             if (Q == 0 && J == 1)
-                dedr_level<TJ, ND, true>(J, hbase_of(J), st, a, b, da, db, Y, i, npad);
+                dedr_level<TJ, ND, true>(J, Jn, ebn, st, a, b, da, db, Y, i, npad);
             else
-                dedr_level<TJ, ND, false>(J, hbase_of(J) + Q * (J + 1), st, a, b, da, db, Y, i,
-                                          npad);
+                dedr_level<TJ, ND, false>(J, Jn, ebn, st, a, b, da, db, Y, i, npad);
             if (J == 2 * Q + 1 && 2 * Q + 2 <= TJ) {
                 mirror_seed<TJ, Q>(st.col, st.seed);
 #pragma unroll
@@ -132,13 +150,17 @@ __device__ __forceinline__ void dedr_column(DedrState<TJ, ND> &st, double2 a, do
         int eb = hbase_of(J0) + Q * (J0 + 1);
 #pragma unroll 1
         for (int J = J0; J <= TJ; ++J) {
-            dedr_level<TJ, ND, false>(J, eb, st, a, b, da, db, Y, i, npad);
+            const int ebnext = eb + (J + 1) * (J / 2 + 1) + Q;  // half index of (J+1, 0, Q)
+            if (J < TJ)
+                dedr_level<TJ, ND, false>(J, J + 1, ebnext, st, a, b, da, db, Y, i, npad);
+            else
+                dedr_level<TJ, ND, false>(J, JN, EBN, st, a, b, da, db, Y, i, npad);
             if (J == 2 * Q + 1 && 2 * Q + 2 <= TJ) {
                 mirror_seed<TJ, Q>(st.col, st.seed);
 #pragma unroll
                 for (int d = 0; d < ND; ++d) mirror_seed<TJ, Q>(st.dcol[d], st.dseed[d]);
             }
-            eb += (J + 1) * (J / 2 + 1) + Q;  // half index of (J+1, 0, Q)
+            eb = ebnext;
         }
     }
 }
@@ -169,11 +191,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
                                              const double2 *__restrict__ Y, Geom g,
                                              double *__restrict__ dE)
 {
-    const int t = blockIdx.x * 64 + threadIdx.x;
-    const int dir0 = (ND == 3) ? 0 : (int)blockIdx.y;
+    // Workgroup w runs on XCD w % 8; it takes the logical block
+    // (w % 8) * per + w / 8, so each XCD works through a contiguous eighth of
+    // the pairs and reads the Y~ of a contiguous eighth of the atoms into its
+    // own L2.  The logical block is (pair block, direction), directions
+    // innermost.
+    constexpr int NDIR = 3 / ND;
+    const int nblk = (npairs + 63) / 64;
+    const int per = (nblk * NDIR + 7) / 8;
+    const int w = (int)blockIdx.x;
+    const int L = (w & 7) * per + (w >> 3);
+    if (L >= nblk * NDIR) return;
+    const int blk = L / NDIR;
+    const int dir0 = (ND == 3) ? 0 : L - blk * NDIR;
+    const int t = blk * 64 + threadIdx.x;
     const bool valid = t < npairs;
     const int tt = valid ? t : npairs - 1;
     const int i = pair_atom[tt];
+    // Y~ of J = 0 and of the first level of column 0, ahead of the geometry
+    const double y00 = load_row(Y, 0, npad, (unsigned)i * 16u).x;
     double rv[3];
     min_image(pos, i, nbr[tt], g, rv);
     PairGeom pg;
@@ -199,7 +235,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     }
 
     DedrState<TJ, ND> st;
-    st.S0 = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) st.S[d] = 0.0;
 #pragma unroll
@@ -208,6 +243,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 #pragma unroll
         for (int d = 0; d < ND; ++d) st.dseed[d][p] = make_double2(0.0, 0.0);
     }
+    if constexpr (TJ >= 1) load_level<TJ>(st.y, 1, hbase_of(1), Y, (unsigned)i, npad);
+    st.S0 = y00;  // J = 0: poly = 1, dpoly = 0
     DedrColumns<TJ, ND, 0>::run(st, pg.a, pg.b, da, db, Y, (unsigned)i, npad);
     if (valid) {
 #pragma unroll
@@ -221,12 +258,16 @@ hipError_t launch_dedr_t(int dirs, int npairs, int npad, const double *pos, cons
                          const int *pair_atom, const double2 *Y, const Geom &g, double *dE,
                          hipStream_t s)
 {
+    // one workgroup per (64 pairs, direction group), padded to a multiple of
+    // 8 for the XCD mapping in the kernel (the padding exits at once)
     const int nblk = (npairs + 63) / 64;
+    const int nlog = nblk * (dirs == 3 ? 1 : 3);
+    const int ngrid = ((nlog + 7) / 8) * 8;
     if (dirs == 3)
-        hipLaunchKernelGGL((k_dedr<TJ, 3>), dim3(nblk, 1), dim3(64), 0, s, npairs, npad, pos, nbr,
+        hipLaunchKernelGGL((k_dedr<TJ, 3>), dim3(ngrid), dim3(64), 0, s, npairs, npad, pos, nbr,
                            pair_atom, Y, g, dE);
     else
-        hipLaunchKernelGGL((k_dedr<TJ, 1>), dim3(nblk, 3), dim3(64), 0, s, npairs, npad, pos, nbr,
+        hipLaunchKernelGGL((k_dedr<TJ, 1>), dim3(ngrid), dim3(64), 0, s, npairs, npad, pos, nbr,
                            pair_atom, Y, g, dE);
     return hipGetLastError();
 }

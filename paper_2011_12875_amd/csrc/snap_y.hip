@@ -35,7 +35,8 @@ __device__ __forceinline__ int hbase_rt(int J)
 
 // Full row px of U^Jx (true values), elements f = fbase(Jx) + px (Jx+1) + q:
 // one buffer descriptor for the row (scalar registers), the element offset
-// in the scalar offset, the atom in the lane offset.
+// in the scalar offset, the atom in the lane offset.  Entries q > Jx are
+// zero, so that products with them vanish.
 template <int TJ>
 __device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int px,
                                               const double2 *__restrict__ U, int npad,
@@ -45,18 +46,24 @@ __device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int 
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)base, (short)0, (Jx + 1) * npad * 16, 0x00020000);
 #pragma unroll
-    for (int q = 0; q <= TJ; ++q)
+    for (int q = 0; q <= TJ; ++q) {
+        r[q] = make_double2(0.0, 0.0);
         if (q <= Jx) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, q * npad * 16, 0);
             r[q] = make_double2(
                 __builtin_bit_cast(double, (unsigned long long)v[0] | ((unsigned long long)v[1] << 32)),
                 __builtin_bit_cast(double, (unsigned long long)v[2] | ((unsigned long long)v[3] << 32)));
         }
+    }
 }
 
 // One contribution (J1, J2 -> J) to row p of Y, accumulated into acc[q].
-// All bounds are wavefront-uniform (scalar branches); q2 = q - q1 + D is a
-// compile-time index into the second row.
+// q2 = q - q1 + D is a compile-time index into the second row.  Every
+// (q, q1) with q1, q2 in [0, 2J_max] is evaluated without a test: rows are
+// zero beyond J1 and J2 and the staged column coefficients beyond J1, so
+// the terms outside the Clebsch-Gordan range add exact zeros (about 6 % of
+// the products at 2J = 8); only the row index q < nq is tested, once per q.
+// The coefficients sit at compile-time offsets cq[q (2J_max + 1) + q1].
 template <int TJ, int D>
 __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, int cp_off, int p,
                                           int nq, const double2 *__restrict__ U, int npad,
@@ -66,8 +73,8 @@ __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, in
     for (int p1 = p1lo; p1 <= p1hi; ++p1) {
         const int p2 = p - p1 + D;
         // re-derive the bounds in every iteration: hoisted out of the loop,
-        // the ~(J/2+1)(J+1) guard compares below would each hold a scalar
-        // register for the whole loop and spill
+        // the guard compares below would each hold a scalar register for the
+        // whole loop and spill
         int j1 = J1, j2 = J2, qn = nq;
         asm volatile("" : "+s"(j1), "+s"(j2), "+s"(qn));
         double2 r1[TJ + 1], r2[TJ + 1];
@@ -77,13 +84,12 @@ __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, in
 #pragma unroll
         for (int q = 0; q <= TJ / 2; ++q)
             if (q < qn) {
-                const int q1lo = q + D - j2;  // q2 <= J2
                 double sr = 0.0, si = 0.0;
 #pragma unroll
                 for (int q1 = 0; q1 <= TJ; ++q1) {
                     const int q2 = q - q1 + D;  // compile-time
-                    if (q2 >= 0 && q2 <= TJ && q1 <= j1 && q1 >= q1lo) {
-                        const double c = cq[q * (j1 + 1) + q1];
+                    if (q2 >= 0 && q2 <= TJ) {
+                        const double c = cq[q * (TJ + 1) + q1];
                         const double2 x = r1[q1], y = r2[q2 < 0 ? 0 : (q2 > TJ ? TJ : q2)];
                         const double pr = x.x * y.x - x.y * y.y;
                         const double pi = x.x * y.y + x.y * y.x;
@@ -169,9 +175,12 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
         const int cp_off = __builtin_amdgcn_readfirstlane(C->cp_off);
         const int cq_off = __builtin_amdgcn_readfirstlane(C->cq_off);
         const int cl = __builtin_amdgcn_readfirstlane(C->l);
-        // stage this contribution's cq table in the wavefront's LDS slice
-        const int ncq = nq * (J1 + 1);
-        for (int k = lane; k < ncq; k += 64) cqs[w][k] = cqt[cq_off + k];
+        // stage this contribution's cq table in the wavefront's LDS slice,
+        // rows padded with zeros to 2J_max + 1 entries
+        for (int k = lane; k < nq * (TJ + 1); k += 64) {
+            const int q = k / (TJ + 1), q1 = k - q * (TJ + 1);
+            cqs[w][k] = (q1 <= J1) ? cqt[cq_off + q * (J1 + 1) + q1] : 0.0;
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
