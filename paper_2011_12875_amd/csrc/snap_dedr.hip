@@ -49,6 +49,8 @@ __device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ,
             double dnr[ND], dni[ND];
 #pragma unroll
             for (int d = 0; d < ND; ++d) dnr[d] = dni[d] = 0.0;
+            // every component is one running sum of products (a single
+            // multiply, then fused multiply-adds)
             if (p < J) {
                 const double2 u = st.col[p];
                 nr = a.x * u.x + a.y * u.y;
@@ -59,23 +61,23 @@ __device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ,
                     dni[d] = da[d].x * u.y - da[d].y * u.x;
                     if (!DZ) {
                         const double2 du = st.dcol[d][p];
-                        dnr[d] += a.x * du.x + a.y * du.y;
-                        dni[d] += a.x * du.y - a.y * du.x;
+                        dnr[d] = dnr[d] + a.x * du.x + a.y * du.y;
+                        dni[d] = dni[d] + a.x * du.y - a.y * du.x;
                     }
                 }
             }
             if (p > 0) {
                 const double2 w = st.col[p - 1];
-                nr -= b.x * w.x + b.y * w.y;
-                ni -= b.x * w.y - b.y * w.x;
+                nr = nr - b.x * w.x - b.y * w.y;
+                ni = ni - b.x * w.y + b.y * w.x;
 #pragma unroll
                 for (int d = 0; d < ND; ++d) {
-                    dnr[d] -= db[d].x * w.x + db[d].y * w.y;
-                    dni[d] -= db[d].x * w.y - db[d].y * w.x;
+                    dnr[d] = dnr[d] - db[d].x * w.x - db[d].y * w.y;
+                    dni[d] = dni[d] - db[d].x * w.y + db[d].y * w.x;
                     if (!DZ) {
                         const double2 dw = st.dcol[d][p - 1];
-                        dnr[d] -= b.x * dw.x + b.y * dw.y;
-                        dni[d] -= b.x * dw.y - b.y * dw.x;
+                        dnr[d] = dnr[d] - b.x * dw.x - b.y * dw.y;
+                        dni[d] = dni[d] - b.x * dw.y + b.y * dw.x;
                     }
                 }
             }

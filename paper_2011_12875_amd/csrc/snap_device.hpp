@@ -137,6 +137,8 @@ __device__ __forceinline__ void poly_step(int J, double2 (&col)[TJ + 1], double2
 #pragma unroll
     for (int p = TJ; p >= 0; --p)
         if (p <= J) {
+            // each component is one running sum of products, so that it
+            // contracts to a single multiply followed by fused multiply-adds
             double nr = 0.0, ni = 0.0;
             if (p < J) {
                 const double2 u = col[p];
@@ -145,8 +147,8 @@ __device__ __forceinline__ void poly_step(int J, double2 (&col)[TJ + 1], double2
             }
             if (p > 0) {
                 const double2 w = col[p - 1];
-                nr -= b.x * w.x + b.y * w.y;
-                ni -= b.x * w.y - b.y * w.x;
+                nr = nr - b.x * w.x - b.y * w.y;
+                ni = ni - b.x * w.y + b.y * w.x;
             }
             col[p] = make_double2(nr, ni);
         }
