@@ -9,50 +9,30 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // compute_U
 //
-// Lanes are pairs: a workgroup is one wavefront holding two atoms of 32 pair
-// slots each (neighbour lists longer than 32 run in chunks).  The stored half
-// (q <= J/2) of every u_j is produced column by column by the recursion of
-// eq. (hysphrecur) on the unnormalised polynomial coefficients; the start of
-// column q+1 is column q at level 2q+1, mirrored.
+// A workgroup is one wavefront holding four atoms of 16 lanes each; every
+// lane walks two pairs of its atom in lockstep (neighbours 32c + slot and
+// 32c + 16 + slot of chunk c; neighbour lists longer than 32 run in chunks)
+// and stages the sum of the two.  The per-atom sum over the 16 lanes then
+// runs on all 64 lanes of the wavefront (4 atoms x 16 staged elements).
 //
-// Each column has its own workgroup (one per column and pair of atoms).  The
-// workgroup of column Q first reruns the short seed path -- levels 2q and
-// 2q+1 of every column q < Q -- and then the levels 2Q..2J_max of column Q.
-// Both parts together cost (2J_max+1)(2J_max+2)/2 elements whatever Q is (45
-// at 2J = 8), so the columns are evenly loaded, and there are J_max + 1
-// times more wavefronts to hide latency with than with one workgroup per
-// atom pair, for 70 extra elements per pair at 2J = 8 (225 instead of 155).
+// The stored half (q <= J/2) of every u_j is produced column by column by
+// the recursion of eq. (hysphrecur) on the unnormalised polynomial
+// coefficients; the start of column q+1 is column q at level 2q+1,
+// mirrored.  Each column has its own workgroup (one per column and group of
+// four atoms).  The workgroup of column Q first reruns the short seed path
+// -- levels 2q and 2q+1 of every column q < Q -- and then the levels
+// 2Q..2J_max of column Q.  Both parts together cost (2J_max+1)(2J_max+2)/2
+// elements whatever Q is (45 at 2J = 8), so the columns are evenly loaded,
+// for 70 extra elements per pair at 2J = 8 (225 instead of 155).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int hbase_of_rt(int J)
-{
-    int s = 0;
-    for (int k = 0; k < J; ++k) s += (k + 1) * (k / 2 + 1);
-    return s;
-}
-
 constexpr int kUStage = 16;  // staged elements per LDS flush (>= twojmax + 1)
-constexpr int kUSlots = 32;  // pair slots per atom (two atoms per wavefront)
+constexpr int kUAtoms = 4;   // atoms per wavefront
+constexpr int kUSlots = 16;  // lanes per atom
+constexpr int kUChunk = 2 * kUSlots;  // pairs per atom per chunk
 
-// elements of column Q: levels J = (Q ? 2Q : 0)..TJ, J+1 each
-constexpr int col_size(int TJ, int Q)
-{
-    int s = 0;
-    for (int j = (Q ? 2 * Q : 0); j <= TJ; ++j) s += j + 1;
-    return s;
-}
-// position of the first element of level J within column Q
-constexpr int col_pos(int TJ, int Q, int J)
-{
-    int s = 0;
-    for (int j = (Q ? 2 * Q : 0); j < J; ++j) s += j + 1;
-    return s;
-}
-
-// LDS of one workgroup: the staged values of both atoms' slots, the
-// column position of each staged slot, and the element table of the
-// column (full-matrix index, mirror index, normalisation, mirror sign),
-// loaded at the start of the kernel alongside the neighbour list.
-template <int TJ>
+// LDS of one workgroup: staged values of the four atoms' lanes, the element
+// of each staged slot, and the element table (full-matrix index, mirror
+// index, normalisation, mirror sign).
 struct UStage {
     double2 v[kUStage][65];
     int code[kUStage];
@@ -87,25 +67,25 @@ constexpr int stage_end(int TJ, int Q)
     return last.slot + TJ + 1;
 }
 
-// Sum the NST staged values of both atoms over their 32 slots and add them
-// to U, stored as full matrices of true values: U(p, q) = N * sum and its
-// mirror U(J-p, J-q) = (-1)^(p-q) conj(U(p, q)).  The first chunk of
+// Sum the NST staged values of the four atoms over their 16 lanes and add
+// them to U, stored as full matrices of true values: U(p, q) = N * sum and
+// its mirror U(J-p, J-q) = (-1)^(p-q) conj(U(p, q)).  The first chunk of
 // neighbours starts from w_self on the diagonal (where N = 1).
-template <int NST, int TJ>
-__device__ __forceinline__ void u_flush(UStage<TJ> &st, int lane, int i0, int n, int npad,
-                                        int chunk, double wself, double2 *__restrict__ U)
+template <int NST>
+__device__ __forceinline__ void u_flush(UStage &st, int lane, int i0, int n, int npad, int chunk,
+                                        double wself, double2 *__restrict__ U)
 {
     __syncthreads();
 #pragma unroll
-    for (int k0 = 0; k0 < 2 * NST; k0 += 64) {
+    for (int k0 = 0; k0 < kUAtoms * NST; k0 += 64) {
         const int k = k0 + lane;
-        if (k < 2 * NST) {
-            const int hh = k >= NST ? 1 : 0;
+        if (k < kUAtoms * NST) {
+            const int hh = k / NST;
             const int ss = k - hh * NST;
             const int code = st.code[ss];
             const UInfo ui = st.table[code & 0xffffff];
             double sr = 0.0, si = 0.0;
-#pragma unroll 8
+#pragma unroll
             for (int j = 0; j < kUSlots; ++j) {
                 const double2 v = st.v[ss][hh * kUSlots + j];
                 sr += v.x;
@@ -132,148 +112,188 @@ __device__ __forceinline__ void u_flush(UStage<TJ> &st, int lane, int i0, int n,
     __syncthreads();
 }
 
+// the two pairs a lane walks: geometry and recursion state
+template <int TJ>
+struct UPair2 {
+    double2 a0, b0, a1, b1;
+    double2 c0[TJ + 1], c1[TJ + 1];  // current column of each pair
+    double2 s0[TJ + 1], s1[TJ + 1];  // seed of the next column
+};
+
+template <int TJ>
+__device__ __forceinline__ void step2(int J, UPair2<TJ> &w)
+{
+    poly_step<TJ>(J, w.c0, w.a0, w.b0);
+    poly_step<TJ>(J, w.c1, w.a1, w.b1);
+#pragma unroll
+    for (int p = 0; p <= TJ; ++p)
+        if (p <= J) {
+            pin(w.c0[p]);
+            pin(w.c1[p]);
+        }
+}
+
 template <int TJ, int Q, int J>
-__device__ __forceinline__ void u_emit(UStage<TJ> &st, int lane, const double2 (&col)[TJ + 1],
-                                       int i0, int n, int npad, int chunk, double wself,
-                                       double2 *__restrict__ U)
+__device__ __forceinline__ void u_emit(UStage &st, int lane, const UPair2<TJ> &w, int i0, int n,
+                                       int npad, int chunk, double wself, double2 *__restrict__ U)
 {
     constexpr StagePos sp = stage_pos(TJ, Q, J);
-    if constexpr (sp.flushed > 0) u_flush<sp.flushed, TJ>(st, lane, i0, n, npad, chunk, wself, U);
-    constexpr int cpos = hbase_of(J) + Q * (J + 1);
+    if constexpr (sp.flushed > 0) u_flush<sp.flushed>(st, lane, i0, n, npad, chunk, wself, U);
+    constexpr int ebase = hbase_of(J) + Q * (J + 1);
 #pragma unroll
     for (int p = 0; p <= J; ++p) {
-        st.v[sp.slot + p][lane] = col[p];  // already carries f_c
-        if (lane == 0) st.code[sp.slot + p] = (cpos + p) | ((p == Q) ? (1 << 24) : 0);
+        // the two pairs' f_c u, summed
+        st.v[sp.slot + p][lane] = make_double2(w.c0[p].x + w.c1[p].x, w.c0[p].y + w.c1[p].y);
+        if (lane == 0) st.code[sp.slot + p] = (ebase + p) | ((p == Q) ? (1 << 24) : 0);
     }
 }
 
 // Levels J..TJ of column Q, each emitted to the staging buffer.
 template <int TJ, int Q, int J>
 struct ULevels {
-    __device__ __forceinline__ static void run(UStage<TJ> &st, int lane, double2 a, double2 b,
-                                               double2 (&col)[TJ + 1], int i0, int n, int npad,
-                                               int chunk, double wself, double2 *__restrict__ U)
+    __device__ __forceinline__ static void run(UStage &st, int lane, UPair2<TJ> &w, int i0, int n,
+                                               int npad, int chunk, double wself,
+                                               double2 *__restrict__ U)
     {
-        poly_step<TJ>(J, col, a, b);
-        u_emit<TJ, Q, J>(st, lane, col, i0, n, npad, chunk, wself, U);
-#pragma unroll
-        for (int p = 0; p <= J; ++p) pin(col[p]);
+        step2<TJ>(J, w);
+        u_emit<TJ, Q, J>(st, lane, w, i0, n, npad, chunk, wself, U);
         memory_fence_compiler();
-        ULevels<TJ, Q, J + 1>::run(st, lane, a, b, col, i0, n, npad, chunk, wself, U);
+        ULevels<TJ, Q, J + 1>::run(st, lane, w, i0, n, npad, chunk, wself, U);
     }
 };
 template <int TJ, int Q>
 struct ULevels<TJ, Q, TJ + 1> {
-    __device__ __forceinline__ static void run(UStage<TJ> &, int, double2, double2,
-                                               double2 (&)[TJ + 1], int, int, int, int, double,
-                                               double2 *__restrict__)
+    __device__ __forceinline__ static void run(UStage &, int, UPair2<TJ> &, int, int, int, int,
+                                               double, double2 *__restrict__)
     {
     }
 };
+
+// Start column q of both pairs: from the seed, or from f_c at level 0.
+template <int TJ, int q>
+__device__ __forceinline__ void start_column(UPair2<TJ> &w, double fc0, double fc1)
+{
+#pragma unroll
+    for (int p = 0; p <= TJ; ++p) {
+        w.c0[p] = (q > 0 && p < 2 * q) ? w.s0[p] : make_double2(0.0, 0.0);
+        w.c1[p] = (q > 0 && p < 2 * q) ? w.s1[p] : make_double2(0.0, 0.0);
+    }
+    if constexpr (q == 0) {
+        // the recursion is linear in its starting column: starting from f_c
+        // instead of 1 yields f_c u directly
+        w.c0[0] = make_double2(fc0, 0.0);
+        w.c1[0] = make_double2(fc1, 0.0);
+    }
+}
 
 // Seed path: column q from its seed, levels up to 2q+1, mirrored into the
 // seed of column q+1; for q = 0 .. Q-1.  Nothing is emitted.
 template <int TJ, int q, int Q>
 struct USeedPath {
-    __device__ __forceinline__ static void run(double fc, double2 a, double2 b,
-                                               double2 (&col)[TJ + 1], double2 (&seed)[TJ + 1])
+    __device__ __forceinline__ static void run(UPair2<TJ> &w, double fc0, double fc1)
     {
         if constexpr (q < Q) {
+            start_column<TJ, q>(w, fc0, fc1);
 #pragma unroll
-            for (int p = 0; p <= TJ; ++p)
-                col[p] = (q > 0 && p < 2 * q) ? seed[p] : make_double2(0.0, 0.0);
-            if constexpr (q == 0) col[0] = make_double2(fc, 0.0);
+            for (int J = (q == 0 ? 1 : 2 * q); J <= 2 * q + 1; ++J) step2<TJ>(J, w);
+            mirror_seed<TJ, q>(w.c0, w.s0);
+            mirror_seed<TJ, q>(w.c1, w.s1);
 #pragma unroll
-            for (int J = (q == 0 ? 1 : 2 * q); J <= 2 * q + 1; ++J) {
-                poly_step<TJ>(J, col, a, b);
-#pragma unroll
-                for (int p = 0; p <= J; ++p) pin(col[p]);
+            for (int p = 0; p <= 2 * q + 1; ++p) {
+                pin(w.s0[p]);
+                pin(w.s1[p]);
             }
-            mirror_seed<TJ, q>(col, seed);
-#pragma unroll
-            for (int p = 0; p <= 2 * q + 1; ++p) pin(seed[p]);
-            USeedPath<TJ, q + 1, Q>::run(fc, a, b, col, seed);
+            USeedPath<TJ, q + 1, Q>::run(w, fc0, fc1);
         }
     }
 };
 
 // Column Q of one chunk of pairs: seed path, column walk, final flush.
 template <int TJ, int Q>
-__device__ __forceinline__ void u_column(UStage<TJ> &st, int lane, double fc, double2 a,
-                                         double2 b, int i0, int n, int npad, int chunk,
+__device__ __forceinline__ void u_column(UStage &st, int lane, UPair2<TJ> &w, double fc0,
+                                         double fc1, int i0, int n, int npad, int chunk,
                                          double wself, double2 *__restrict__ U)
 {
-    double2 col[TJ + 1], seed[TJ + 1];
 #pragma unroll
-    for (int p = 0; p <= TJ; ++p) seed[p] = make_double2(0.0, 0.0);
-    USeedPath<TJ, 0, Q>::run(fc, a, b, col, seed);
-#pragma unroll
-    for (int p = 0; p <= TJ; ++p) col[p] = (Q > 0 && p < 2 * Q) ? seed[p] : make_double2(0.0, 0.0);
-    if constexpr (Q == 0) {
-        // the recursion is linear in its starting column: starting from f_c
-        // instead of 1 yields f_c u directly
-        col[0] = make_double2(fc, 0.0);
-        u_emit<TJ, 0, 0>(st, lane, col, i0, n, npad, chunk, wself, U);
-    }
-    ULevels<TJ, Q, (Q == 0 ? 1 : 2 * Q)>::run(st, lane, a, b, col, i0, n, npad, chunk, wself, U);
-    u_flush<stage_end(TJ, Q), TJ>(st, lane, i0, n, npad, chunk, wself, U);
+    for (int p = 0; p <= TJ; ++p) w.s0[p] = w.s1[p] = make_double2(0.0, 0.0);
+    USeedPath<TJ, 0, Q>::run(w, fc0, fc1);
+    start_column<TJ, Q>(w, fc0, fc1);
+    if constexpr (Q == 0) u_emit<TJ, 0, 0>(st, lane, w, i0, n, npad, chunk, wself, U);
+    ULevels<TJ, Q, (Q == 0 ? 1 : 2 * Q)>::run(st, lane, w, i0, n, npad, chunk, wself, U);
+    u_flush<stage_end(TJ, Q)>(st, lane, i0, n, npad, chunk, wself, U);
 }
 
 // uniform column index -> compile-time instance
 template <int TJ, int Q>
 struct UColumn {
-    __device__ __forceinline__ static void run(int col, UStage<TJ> &st, int lane, double fc,
-                                               double2 a, double2 b, int i0, int n, int npad,
+    __device__ __forceinline__ static void run(int col, UStage &st, int lane, UPair2<TJ> &w,
+                                               double fc0, double fc1, int i0, int n, int npad,
                                                int chunk, double wself, double2 *__restrict__ U)
     {
         if constexpr (Q <= TJ / 2) {
             if (col == Q)
-                u_column<TJ, Q>(st, lane, fc, a, b, i0, n, npad, chunk, wself, U);
+                u_column<TJ, Q>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
             else
-                UColumn<TJ, Q + 1>::run(col, st, lane, fc, a, b, i0, n, npad, chunk, wself, U);
+                UColumn<TJ, Q + 1>::run(col, st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
         }
     }
 };
 
-template <int TJ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TJ <= 10 ? 3 : 2, 8))) void k_compute_u(int n, int npad, const double *__restrict__ pos,
-                                                  const int *__restrict__ off,
-                                                  const int *__restrict__ nbr, Geom g,
-                                                  const UInfo *__restrict__ uinfo,
-                                                  double2 *__restrict__ U,
-                                                  int *__restrict__ pair_atom,
-                                                  int *__restrict__ flag)
+// geometry of neighbour slot s of atom i (a = 1, b = 0, f_c = 0 when empty)
+__device__ __forceinline__ void slot_geometry(bool valid, int i, int t, bool first,
+                                              const double *__restrict__ pos,
+                                              const int *__restrict__ nbr, const Geom &g,
+                                              int *__restrict__ pair_atom, int *__restrict__ flag,
+                                              PairGeom &pg)
 {
-    __shared__ UStage<TJ> st;
+    pg.a = make_double2(1.0, 0.0);
+    pg.b = make_double2(0.0, 0.0);
+    pg.fc = 0.0;
+    if (valid) {
+        if (first) pair_atom[t] = i;
+        double rv[3];
+        min_image(pos, i, nbr[t], g, rv);
+        if (!pair_geometry(rv, g, pg) && first) flag[0] = 1;
+    }
+}
+
+template <int TJ>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_compute_u(
+    int n, int npad, const double *__restrict__ pos, const int *__restrict__ off,
+    const int *__restrict__ nbr, Geom g, const UInfo *__restrict__ uinfo, double2 *__restrict__ U,
+    int *__restrict__ pair_atom, int *__restrict__ flag)
+{
+    __shared__ UStage st;
     constexpr int NCOL = TJ / 2 + 1;
     const int lane = threadIdx.x;
     const int colq = (int)blockIdx.x % NCOL;  // uniform
     if (lane == 0) st.table = uinfo;  // read after the first flush's barrier
-    const int h = lane >> 5, slot = lane & 31;
-    const int i0 = ((int)blockIdx.x / NCOL) * 2;
+    const int h = lane / kUSlots, slot = lane % kUSlots;
+    const int i0 = ((int)blockIdx.x / NCOL) * kUAtoms;
     const int i = i0 + h;
-    const int nA = (i0 < n) ? off[i0 + 1] - off[i0] : 0;
-    const int nB = (i0 + 1 < n) ? off[i0 + 2] - off[i0 + 1] : 0;
-    const int mx = nA > nB ? nA : nB;
-    const int nchunk = mx > 0 ? (mx + kUSlots - 1) / kUSlots : 1;
-    const int myn = h ? nB : nA;
+    int mx = 0;
+#pragma unroll
+    for (int k = 0; k < kUAtoms; ++k) {
+        const int cnt = (i0 + k < n) ? off[i0 + k + 1] - off[i0 + k] : 0;
+        mx = cnt > mx ? cnt : mx;
+    }
+    const int nchunk = mx > 0 ? (mx + kUChunk - 1) / kUChunk : 1;
+    const int myn = (i < n) ? off[i + 1] - off[i] : 0;
     const int mybeg = (i < n) ? off[i] : 0;
 
+    UPair2<TJ> w;
     for (int c = 0; c < nchunk; ++c) {
-        const int s = c * kUSlots + slot;
-        const bool valid = (i < n) && (s < myn);
-        const int t = mybeg + s;
-        PairGeom pg;
-        pg.a = make_double2(1.0, 0.0);
-        pg.b = make_double2(0.0, 0.0);
-        pg.fc = 0.0;
-        if (valid) {
-            if (colq == 0) pair_atom[t] = i;
-            double rv[3];
-            min_image(pos, i, nbr[t], g, rv);
-            if (!pair_geometry(rv, g, pg) && colq == 0) flag[0] = 1;
-        }
-        UColumn<TJ, 0>::run(colq, st, lane, pg.fc, pg.a, pg.b, i0, n, npad, c, g.wself, U);
+        const int s0 = c * kUChunk + slot, s1 = s0 + kUSlots;
+        PairGeom g0, g1;
+        slot_geometry((i < n) && (s0 < myn), i, mybeg + s0, colq == 0, pos, nbr, g, pair_atom,
+                      flag, g0);
+        slot_geometry((i < n) && (s1 < myn), i, mybeg + s1, colq == 0, pos, nbr, g, pair_atom,
+                      flag, g1);
+        w.a0 = g0.a;
+        w.b0 = g0.b;
+        w.a1 = g1.a;
+        w.b1 = g1.b;
+        UColumn<TJ, 0>::run(colq, st, lane, w, g0.fc, g1.fc, i0, n, npad, c, g.wself, U);
     }
 }
 
@@ -282,7 +302,7 @@ hipError_t launch_u_t(int n, int npad, const double *pos, const int *off, const 
                       const Geom &g, const UInfo *uinfo, double2 *U, int *pair_atom, int *flag,
                       hipStream_t s)
 {
-    const int nblk = ((n + 1) / 2) * (TJ / 2 + 1);
+    const int nblk = ((n + kUAtoms - 1) / kUAtoms) * (TJ / 2 + 1);
     hipLaunchKernelGGL(k_compute_u<TJ>, dim3(nblk), dim3(64), 0, s, n, npad, pos, off, nbr, g,
                        uinfo, U, pair_atom, flag);
     return hipGetLastError();
