@@ -84,6 +84,11 @@ __device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ,
             st.col[p] = make_double2(nr, ni);
 #pragma unroll
             for (int d = 0; d < ND; ++d) st.dcol[d][p] = make_double2(dnr[d], dni[d]);
+            // close each element's live range here (without, the level's
+            // products are interleaved across elements and spill at 2J = 8)
+            pin(st.col[p]);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) pin(st.dcol[d][p]);
         }
 #pragma unroll
     for (int p = 0; p <= TJ; ++p)
