@@ -52,9 +52,12 @@ __global__ void k_energy_from_b(int n, int nb, const double *__restrict__ B,
 // ---------------------------------------------------------------------------
 // update_forces and the energy
 // ---------------------------------------------------------------------------
-// Eight lanes per atom: the lanes stride over the atom's pairs (forces) and
-// over the row partials of the energy, then combine with shuffles in a fixed
-// order.
+// kGatherLanes lanes per atom: the lanes stride over the atom's pairs
+// (forces) and over the row partials of the energy, then combine with
+// shuffles in a fixed order.  One pair per lane for up to 32 neighbours keeps
+// the dependent rev -> dE loads of many atoms in flight at once.
+constexpr int kGatherLanes = 32;
+
 __global__ __launch_bounds__(256) void k_gather(int n, int npad, int nrows,
                                                 const int *__restrict__ off,
                                                 const int *__restrict__ rev,
@@ -63,25 +66,26 @@ __global__ __launch_bounds__(256) void k_gather(int n, int npad, int nrows,
                                                 double *__restrict__ energy,
                                                 double *__restrict__ force)
 {
-    const int g = blockIdx.x * 32 + (threadIdx.x >> 3);
-    const int s = threadIdx.x & 7;
+    constexpr int L = kGatherLanes;
+    const int g = blockIdx.x * (256 / L) + (threadIdx.x / L);
+    const int s = threadIdx.x % L;
     const int i = g < n ? g : n - 1;
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
     const int te = off[i + 1];
-    for (int t = off[i] + s; t < te; t += 8) {
+    for (int t = off[i] + s; t < te; t += L) {
         const int r = rev[t];
         fx += dE[3 * (size_t)t + 0] - dE[3 * (size_t)r + 0];
         fy += dE[3 * (size_t)t + 1] - dE[3 * (size_t)r + 1];
         fz += dE[3 * (size_t)t + 2] - dE[3 * (size_t)r + 2];
     }
     if (energy)
-        for (int k = s; k < nrows; k += 8) e += Epart[(size_t)k * npad + i];
+        for (int k = s; k < nrows; k += L) e += Epart[(size_t)k * npad + i];
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
-        fx += __shfl_xor(fx, m, 8);
-        fy += __shfl_xor(fy, m, 8);
-        fz += __shfl_xor(fz, m, 8);
-        e += __shfl_xor(e, m, 8);
+    for (int m = 1; m < L; m <<= 1) {
+        fx += __shfl_xor(fx, m, L);
+        fy += __shfl_xor(fy, m, L);
+        fz += __shfl_xor(fz, m, L);
+        e += __shfl_xor(e, m, L);
     }
     if (g < n && s == 0) {
         force[3 * (size_t)g + 0] = fx;
@@ -126,8 +130,9 @@ hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *
                          const double *dE, const double *Epart, double *energy, double *force,
                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather, dim3((n + 31) / 32), dim3(256), 0, s, n, npad, nrows, off, rev,
-                       dE, Epart, energy, force);
+    constexpr int apb = 256 / kGatherLanes;  // atoms per block
+    hipLaunchKernelGGL(k_gather, dim3((n + apb - 1) / apb), dim3(256), 0, s, n, npad, nrows, off,
+                       rev, dE, Epart, energy, force);
     return hipGetLastError();
 }
 
