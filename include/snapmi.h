@@ -140,7 +140,8 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
                  double *dE_pair, void *stream);
 
 /* The forward half used by automatic differentiation: compute_U and the
- * bispectrum only.  energy = sum_l beta_l B_l per atom.  Same arguments as
+ * bispectrum only.  energy = sum_l beta_l B_l per atom; energy may be NULL
+ * (then beta is not read and may be NULL too).  Other arguments as in
  * snap_compute; the context keeps U_j of this call for snap_backward. */
 int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
                  const int *off, const int *nbr, const int *rev, const double *beta,

@@ -459,7 +459,7 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
     if (bispec) {
         StageTimer tm(c, 4, s);
         HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, bispec, beta, per_atom_beta, nullptr,
-                                  s),
+                                  s, c->tab.nfullel),
                 "bispectrum launch");
         tm.finish();
     }
@@ -471,9 +471,9 @@ int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double
                  const int *off, const int *nbr, const int *rev, const double *beta,
                  int per_atom_beta, double *energy, double *bispec, void *stream)
 {
-    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta, energy != nullptr);
     if (st) return st;
-    if (n > 0 && (!energy || !bispec)) return fail(SNAP_EINVAL, "NULL output pointer");
+    if (n > 0 && !bispec) return fail(SNAP_EINVAL, "NULL output pointer");
     if ((st = ensure_device(c))) return st;
     if (n == 0) return SNAP_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -481,7 +481,7 @@ int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double
     const Geom g = make_geom(c, box);
     if ((st = run_u(c, n, npairs, pos, g, off, nbr, s))) return st;
     HIP_TRY(launch_bispectrum(n, c->work.npad, c->work.U, c->dev, c->tab.nb, bispec, beta,
-                              per_atom_beta, energy, s),
+                              per_atom_beta, energy, s, c->tab.nfullel),
             "bispectrum launch");
     c->last_n = n;
     return SNAP_OK;
@@ -592,7 +592,8 @@ int snap_jacobian(snap_ctx *c, int n, int npairs, const double *pos, const doubl
     const int nb = c->tab.nb;
     if ((st = run_u(c, n, npairs, pos, g, off, nbr, s))) return st;
     if (bispec)
-        HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, bispec, nullptr, 0, nullptr, s),
+        HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, bispec, nullptr, 0, nullptr, s,
+                                  c->tab.nfullel),
                 "bispectrum launch");
     c->last_n = n;
     if (npairs == 0) return SNAP_OK;

@@ -48,9 +48,11 @@ hipError_t launch_compute_y(int twojmax, int n, int npad, const double2 *U, doub
                             const DevTables &T, const double *beta, int per_atom_beta, int nb,
                             const double *gscale, double *Epart, hipStream_t s);
 
+// B (and, when energy is not NULL, energy = beta . B); nfull = number of full
+// U elements (small 2J stage U in LDS)
 hipError_t launch_bispectrum(int n, int npad, const double2 *U, const DevTables &T, int nb,
                              double *B, const double *beta, int per_atom_beta, double *energy,
-                             hipStream_t s);
+                             hipStream_t s, int nfull);
 
 hipError_t launch_dedr_low(int twojmax, int dirs, int npairs, int npad, const double *pos,
                            const int *nbr, const int *pair_atom, const double2 *Y,

@@ -37,6 +37,44 @@ __global__ __launch_bounds__(64) void k_bispectrum(int n, int npad, const double
     if (atom < n) B[(size_t)atom * nb + l] = bsum;
 }
 
+// The same for small 2J: the U of a block of 64 atoms is staged in LDS once
+// (coalesced), and the four wavefronts of the workgroup share the
+// components, so every Clebsch-Gordan term reads LDS instead of L2.
+template <int NF>
+__global__ __launch_bounds__(256) void k_bispectrum_lds(int n, int npad,
+                                                        const double2 *__restrict__ U,
+                                                        const BTerm *__restrict__ terms,
+                                                        const BItem *__restrict__ bitems,
+                                                        const int *__restrict__ bl_begin, int nb,
+                                                        double *__restrict__ B)
+{
+    __shared__ double2 Us[NF][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int atom = blockIdx.x * 64 + lane;  // < npad
+    for (int f = w; f < NF; f += 4) Us[f][lane] = U[(size_t)f * npad + atom];
+    __syncthreads();
+    for (int l = w; l < nb; l += 4) {
+        double bsum = 0.0;
+        const int xe = bl_begin[l + 1];
+        for (int x = bl_begin[l]; x < xe; ++x) {
+            const BItem *bi = bitems + x;
+            double zr = 0.0, zi = 0.0;
+            const int te = bi->te;
+            for (int tt = bi->tb; tt < te; ++tt) {
+                const BTerm tm = terms[tt];
+                const double2 u1 = Us[tm.f1][lane];
+                const double2 u2 = Us[tm.f2][lane];
+                zr += tm.cc * (u1.x * u2.x - u1.y * u2.y);
+                zi += tm.cc * (u1.x * u2.y + u1.y * u2.x);
+            }
+            const double2 uj = Us[bi->f3][lane];
+            bsum += bi->w * (zr * uj.x + zi * uj.y);
+        }
+        if (atom < n) B[(size_t)atom * nb + l] = bsum;
+    }
+}
+
 __global__ void k_energy_from_b(int n, int nb, const double *__restrict__ B,
                                 const double *__restrict__ beta, int per_atom_beta,
                                 double *__restrict__ energy)
@@ -114,11 +152,19 @@ __global__ void k_unscale(int n, int npad, int nhalf, const double2 *__restrict_
 
 hipError_t launch_bispectrum(int n, int npad, const double2 *U, const DevTables &T, int nb,
                              double *B, const double *beta, int per_atom_beta, double *energy,
-                             hipStream_t s)
+                             hipStream_t s, int nfull)
 {
     const int nblk = (n + 63) / 64;
-    hipLaunchKernelGGL(k_bispectrum, dim3(nblk, nb), dim3(64), 0, s, n, npad, U, T.bterms,
-                       T.bitems, T.bl_begin, nb, B);
+    // full elements sum_{J <= 2Jmax} (J+1)^2: 2J = 4 -> 55, 2J = 5 -> 91
+    if (nfull == 55)
+        hipLaunchKernelGGL(k_bispectrum_lds<55>, dim3(nblk), dim3(256), 0, s, n, npad, U,
+                           T.bterms, T.bitems, T.bl_begin, nb, B);
+    else if (nfull == 91)
+        hipLaunchKernelGGL(k_bispectrum_lds<91>, dim3(nblk), dim3(256), 0, s, n, npad, U,
+                           T.bterms, T.bitems, T.bl_begin, nb, B);
+    else
+        hipLaunchKernelGGL(k_bispectrum, dim3(nblk, nb), dim3(64), 0, s, n, npad, U, T.bterms,
+                           T.bitems, T.bl_begin, nb, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !energy) return e;
     hipLaunchKernelGGL(k_energy_from_b, dim3((n + 127) / 128), dim3(128), 0, s, n, nb, B, beta,

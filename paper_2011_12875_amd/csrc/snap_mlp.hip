@@ -3,7 +3,7 @@
 // components, E_i = f(x_i), x_i = (B_i - mean) * scale, FP32 weights and FP32
 // accumulation, and what training it needs.
 //
-//   k_mlp_forward   E_i, g_i = dE_i/dB_i (the per-atom coefficients that the
+//   k_mlp_forward_w E_i, g_i = dE_i/dB_i (the per-atom coefficients that the
 //                   SNAP adjoint turns into forces) and an out-of-range flag;
 //   k_mlp_grad      per block of 64 atoms, d/dtheta of
 //                   sum_i r_i E_i + v_i . g_i  for given r_i and v_i: ordinary
@@ -61,39 +61,64 @@ __device__ __forceinline__ void silu2(float h, float &a, float &d1)
     d1 = s * (1.0f + h * (1.0f - s));
 }
 
+// The network on a workgroup of four wavefronts and 64 atoms (lane = atom
+// in every wavefront): E_i, g_i = dE_i/dB_i and the range gate.  Wavefront
+// w computes hidden units
+// 16w .. 16w+15 of both layers, so the weights stay wavefront-uniform
+// (scalar loads) while four times as many wavefronts share the work.
+// Activations and partial sums are exchanged through LDS (unit-major,
+// atom-contiguous rows: conflict-free).
+constexpr int kFwdWaves = 4;
+constexpr int kFwdUnits = H / kFwdWaves;
+
 template <int NIN>
-__global__ __launch_bounds__(64) void k_mlp_forward(int n, const float *__restrict__ prm,
-                                                    const float *__restrict__ norm,
-                                                    const float *__restrict__ bounds, float margin,
-                                                    const double *__restrict__ B,
-                                                    double *__restrict__ E,
-                                                    double *__restrict__ g,
-                                                    int *__restrict__ flag)
+__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward_w(
+    int n, const float *__restrict__ prm, const float *__restrict__ norm,
+    const float *__restrict__ bounds, float margin, const double *__restrict__ B,
+    double *__restrict__ E, double *__restrict__ g, int *__restrict__ flag)
 {
     using L = MlpLayout<NIN>;
-    const int i = blockIdx.x * 64 + threadIdx.x;
+    __shared__ float a1s[H][64];               // a1 of the block's atoms
+    __shared__ float part[kFwdWaves][H][64];   // per-wave partial dE/da1, then dE/dx
+    __shared__ float es[kFwdWaves][64];        // per-wave partial energies
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int u0 = w * kFwdUnits;
+    const int i = blockIdx.x * 64 + lane;
     const int ia = i < n ? i : n - 1;
     float x[NIN];
     bool out = false;
 #pragma unroll
     for (int k = 0; k < NIN; ++k) {
         x[k] = (float)((B[(size_t)ia * NIN + k] - (double)norm[k]) * (double)norm[NIN + k]);
-        if (bounds) {
-            const float lo = bounds[k], hi = bounds[NIN + k], w = margin * (hi - lo);
-            out |= !(x[k] >= lo - w && x[k] <= hi + w);  // also catches NaN
+        if (bounds && w == 0) {
+            const float lo = bounds[k], hi = bounds[NIN + k], wd = margin * (hi - lo);
+            out |= !(x[k] >= lo - wd && x[k] <= hi + wd);  // also catches NaN
         }
     }
-    float a1[H], s1[H], d1[H];
+    // layer 1, own units
+    float s1[kFwdUnits];
 #pragma unroll
-    for (int j = 0; j < H; ++j) {
+    for (int jj = 0; jj < kFwdUnits; ++jj) {
+        const int j = u0 + jj;
         float h = prm[L::B1 + j];
 #pragma unroll
         for (int k = 0; k < NIN; ++k) h += prm[L::W1 + j * NIN + k] * x[k];
-        silu2(h, a1[j], s1[j]);
-        d1[j] = 0.0f;
+        float a;
+        silu2(h, a, s1[jj]);
+        a1s[j][lane] = a;
     }
-    float e = prm[L::B3];
-    for (int j = 0; j < H; ++j) {
+    __syncthreads();
+    // layer 2, own units; partial back-propagation to all of a1
+    float a1[H], d1[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        a1[k] = a1s[k][lane];
+        d1[k] = 0.0f;
+    }
+    float e = 0.0f;
+    for (int jj = 0; jj < kFwdUnits; ++jj) {
+        const int j = u0 + jj;
         float h = prm[L::B2 + j];
 #pragma unroll
         for (int k = 0; k < H; ++k) h += prm[L::W2 + j * H + k] * a1[k];
@@ -105,19 +130,40 @@ __global__ __launch_bounds__(64) void k_mlp_forward(int n, const float *__restri
 #pragma unroll
         for (int k = 0; k < H; ++k) d1[k] += prm[L::W2 + j * H + k] * d2;
     }
+#pragma unroll
+    for (int k = 0; k < H; ++k) part[w][k][lane] = d1[k];
+    es[w][lane] = e;
+    __syncthreads();
+    // own units of layer 1: sum the four partials, through silu', to dE/dx
     float gx[NIN];
 #pragma unroll
     for (int m = 0; m < NIN; ++m) gx[m] = 0.0f;
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-        const float d = d1[k] * s1[k];
+    for (int jj = 0; jj < kFwdUnits; ++jj) {
+        const int j = u0 + jj;
+        float d = 0.0f;
 #pragma unroll
-        for (int m = 0; m < NIN; ++m) gx[m] += prm[L::W1 + k * NIN + m] * d;
+        for (int v = 0; v < kFwdWaves; ++v) d += part[v][j][lane];
+        d *= s1[jj];
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) gx[m] += prm[L::W1 + j * NIN + m] * d;
     }
-    if (i < n) {
-        E[i] = (double)e;
+    __syncthreads();  // everyone has read part: reuse it for dE/dx
 #pragma unroll
-        for (int m = 0; m < NIN; ++m) g[(size_t)i * NIN + m] = (double)gx[m] * (double)norm[NIN + m];
+    for (int m = 0; m < NIN; ++m) part[w][m][lane] = gx[m];
+    __syncthreads();
+    if (w == 0 && i < n) {
+        float et = prm[L::B3];
+#pragma unroll
+        for (int v = 0; v < kFwdWaves; ++v) et += es[v][lane];
+        E[i] = (double)et;
+#pragma unroll
+        for (int m = 0; m < NIN; ++m) {
+            float gm = 0.0f;
+#pragma unroll
+            for (int v = 0; v < kFwdWaves; ++v) gm += part[v][m][lane];
+            g[(size_t)i * NIN + m] = (double)gm * (double)norm[NIN + m];
+        }
         if (out && flag) flag[0] = 1;
     }
 }
@@ -446,8 +492,8 @@ hipError_t launch_mlp_forward(int nin, int n, const float *prm, const float *nor
                               double *g, int *flag, hipStream_t s)
 {
 #define CALL(K)                                                                              \
-    hipLaunchKernelGGL(k_mlp_forward<K>, dim3((n + 63) / 64), dim3(64), 0, s, n, prm, norm, \
-                       bounds, margin, B, E, g, flag)
+    hipLaunchKernelGGL(k_mlp_forward_w<K>, dim3((n + 63) / 64), dim3(64 * kFwdWaves), 0, s, n, \
+                       prm, norm, bounds, margin, B, E, g, flag)
     SNAP_MLP_DISPATCH(nin, CALL)
 #undef CALL
     return hipGetLastError();

@@ -255,12 +255,21 @@ class SnapPotential:
         self._fwd_token += 1  # U of this call replaces that of the last forward
         return out
 
-    def forward(self, pos, box, nl, beta):
-        """compute_U + bispectrum: (E_i, B_i); keeps U for backward()."""
+    def forward(self, pos, box, nl, beta, bispectrum=None):
+        """compute_U + bispectrum: (E_i, B_i); keeps U for backward().  With
+        beta None only B_i is computed (E is None)."""
         import torch
-        n, boxa, per_atom = self._args(pos, box, nl, beta)
-        E = torch.empty(n, dtype=torch.float64, device=pos.device)
-        B = torch.empty((n, self.ncoeff), dtype=torch.float64, device=pos.device)
+        if beta is None:
+            assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+            n = pos.shape[0]
+            assert nl.n == n
+            boxa = (ctypes.c_double * 3)(*[float(x) for x in box])
+            per_atom, E = 0, None
+        else:
+            n, boxa, per_atom = self._args(pos, box, nl, beta)
+            E = torch.empty(n, dtype=torch.float64, device=pos.device)
+        B = bispectrum if bispectrum is not None else torch.empty(
+            (n, self.ncoeff), dtype=torch.float64, device=pos.device)
         _check(load().snap_forward(
             self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
             self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(E), self._ptr(B),

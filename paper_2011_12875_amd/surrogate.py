@@ -344,7 +344,6 @@ class SurrogatePotential:
         import torch
         self.net, self.pot4, self.pot8 = net, pot4, pot8
         self.beta8 = torch.as_tensor(np.asarray(beta8, dtype=np.float64), device="cuda")
-        self.zero4 = torch.zeros(pot4.ncoeff, dtype=torch.float64, device="cuda")
         self.flag = torch.zeros(1, dtype=torch.int32, device="cuda")
         self._bufs = {}
 
@@ -354,7 +353,8 @@ class SurrogatePotential:
             f64 = dict(dtype=torch.float64, device="cuda")
             self._bufs = {"n": n, "E": torch.empty(n, **f64),
                           "g": torch.empty((n, self.pot4.ncoeff), **f64),
-                          "ones": torch.ones(n, **f64), "F": torch.empty((n, 3), **f64)}
+                          "ones": torch.ones(n, **f64), "F": torch.empty((n, 3), **f64),
+                          "B": torch.empty((n, self.pot4.ncoeff), **f64)}
         return self._bufs
 
     def compute(self, pos, box, nl, check=True):
@@ -363,7 +363,7 @@ class SurrogatePotential:
         self.flag later)."""
         b = self._buffers(pos.shape[0])
         self.flag.zero_()
-        _, B = self.pot4.forward(pos, box, nl, self.zero4)
+        _, B = self.pot4.forward(pos, box, nl, None, bispectrum=b["B"])
         E, g = self.net.forward(B, flag=self.flag, energy=b["E"], grad_b=b["g"])
         F = self.pot4.backward(pos, box, nl, g, b["ones"], force=b["F"])
         out = {"energy": E, "force": F, "fallback": False}

@@ -114,6 +114,8 @@ def test_all_twojmax_small(tj):
     o = oracle.snap(pos, box, tj, wl.RCUT, beta=beta)
     _check_energy(g["energy"], o["E"])
     assert np.abs(g["force"] - o["F"]).max() <= F_ABS
+    bscale = np.maximum(np.abs(o["B"]), 1.0)
+    assert (np.abs(g["bispectrum"] - o["B"]) / bscale).max() <= E_REL
 
 
 def test_2j14_sampled():

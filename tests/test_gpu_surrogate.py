@@ -241,7 +241,10 @@ def test_surrogate_forces_match_oracle_chain():
     assert np.abs(out["energy"].cpu().numpy() - Eo).max() <= 3e-5 * np.abs(Eo).max()
     assert np.abs(F - of["F"]).max() <= 3e-5 * np.abs(of["F"]).max()
     _, J = pot4.jacobian(tpos, box, nl)
-    E2, g2 = net.forward(pot4.forward(tpos, box, nl, sp.zero4)[1], gate=False)
+    Ez, Bz = pot4.forward(tpos, box, nl, torch.zeros(14, dtype=torch.float64, device="cuda"))
+    En, Bn = pot4.forward(tpos, box, nl, None)  # B only
+    assert En is None and torch.equal(Bz, Bn)
+    E2, g2 = net.forward(Bn, gate=False)
     F2 = snapmi.jacobian_forces(nl, J, g2).cpu().numpy()
     assert np.abs(F - F2).max() <= 1e-6 * np.abs(F).max()
 
