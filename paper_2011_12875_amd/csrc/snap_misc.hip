@@ -38,10 +38,13 @@ __global__ __launch_bounds__(64) void k_bispectrum(int n, int npad, const double
 }
 
 // The same for small 2J: the U of a block of 64 atoms is staged in LDS once
-// (coalesced), and the four wavefronts of the workgroup share the
-// components, so every Clebsch-Gordan term reads LDS instead of L2.
+// (coalesced), and the workgroup's wavefronts (one per component, up to 16)
+// share the components, so every Clebsch-Gordan term reads LDS instead of
+// L2 and each wavefront walks one component's terms.
+constexpr int kBWaveMax = 16;
+
 template <int NF>
-__global__ __launch_bounds__(256) void k_bispectrum_lds(int n, int npad,
+__global__ __launch_bounds__(64 * kBWaveMax) void k_bispectrum_lds(int n, int npad,
                                                         const double2 *__restrict__ U,
                                                         const BTerm *__restrict__ terms,
                                                         const BItem *__restrict__ bitems,
@@ -51,17 +54,33 @@ __global__ __launch_bounds__(256) void k_bispectrum_lds(int n, int npad,
     __shared__ double2 Us[NF][64];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
     const int atom = blockIdx.x * 64 + lane;  // < npad
-    for (int f = w; f < NF; f += 4) Us[f][lane] = U[(size_t)f * npad + atom];
+    for (int f = w; f < NF; f += nw) Us[f][lane] = U[(size_t)f * npad + atom];
     __syncthreads();
-    for (int l = w; l < nb; l += 4) {
+    for (int l = w; l < nb; l += nw) {
         double bsum = 0.0;
         const int xe = bl_begin[l + 1];
         for (int x = bl_begin[l]; x < xe; ++x) {
             const BItem *bi = bitems + x;
             double zr = 0.0, zi = 0.0;
             const int te = bi->te;
-            for (int tt = bi->tb; tt < te; ++tt) {
+            int tt = bi->tb;
+            // eight terms per step: their (scalar) loads are issued together
+            // instead of one dependent load per term
+            for (; tt + 8 <= te; tt += 8) {
+                BTerm tm[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) tm[k] = terms[tt + k];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double2 u1 = Us[tm[k].f1][lane];
+                    const double2 u2 = Us[tm[k].f2][lane];
+                    zr += tm[k].cc * (u1.x * u2.x - u1.y * u2.y);
+                    zi += tm[k].cc * (u1.x * u2.y + u1.y * u2.x);
+                }
+            }
+            for (; tt < te; ++tt) {
                 const BTerm tm = terms[tt];
                 const double2 u1 = Us[tm.f1][lane];
                 const double2 u2 = Us[tm.f2][lane];
@@ -156,11 +175,12 @@ hipError_t launch_bispectrum(int n, int npad, const double2 *U, const DevTables 
 {
     const int nblk = (n + 63) / 64;
     // full elements sum_{J <= 2Jmax} (J+1)^2: 2J = 4 -> 55, 2J = 5 -> 91
+    const int nw = nb < kBWaveMax ? nb : kBWaveMax;
     if (nfull == 55)
-        hipLaunchKernelGGL(k_bispectrum_lds<55>, dim3(nblk), dim3(256), 0, s, n, npad, U,
+        hipLaunchKernelGGL(k_bispectrum_lds<55>, dim3(nblk), dim3(64 * nw), 0, s, n, npad, U,
                            T.bterms, T.bitems, T.bl_begin, nb, B);
     else if (nfull == 91)
-        hipLaunchKernelGGL(k_bispectrum_lds<91>, dim3(nblk), dim3(256), 0, s, n, npad, U,
+        hipLaunchKernelGGL(k_bispectrum_lds<91>, dim3(nblk), dim3(64 * nw), 0, s, n, npad, U,
                            T.bterms, T.bitems, T.bl_begin, nb, B);
     else
         hipLaunchKernelGGL(k_bispectrum, dim3(nblk, nb), dim3(64), 0, s, n, npad, U, T.bterms,
