@@ -68,7 +68,7 @@ template <int TJ, int D>
 __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, int cp_off, int p,
                                           int nq, const double2 *__restrict__ U, int npad,
                                           unsigned voff, const double *__restrict__ cpt,
-                                          const double *cq, double2 (&acc)[TJ / 2 + 1])
+                                          const double *cq, double f, double2 (&acc)[TJ / 2 + 1])
 {
     for (int p1 = p1lo; p1 <= p1hi; ++p1) {
         const int p2 = p - p1 + D;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, in
         double2 r1[TJ + 1], r2[TJ + 1];
         load_full_row<TJ>(r1, j1, p1, U, npad, voff);
         load_full_row<TJ>(r2, j2, p2, U, npad, voff);
-        const double cpv = cpt[cp_off + (p1 - p1lo)];
+        const double cpv = f * cpt[cp_off + (p1 - p1lo)];
 #pragma unroll
         for (int q = 0; q <= TJ / 2; ++q)
             if (q < qn) {
@@ -109,20 +109,21 @@ struct YDispatch {
                                                int cp_off, int p, int nq,
                                                const double2 *__restrict__ U, int npad,
                                                unsigned voff, const double *__restrict__ cpt,
-                                               const double *cq, double2 (&acc)[TJ / 2 + 1])
+                                               const double *cq, double f,
+                                               double2 (&acc)[TJ / 2 + 1])
     {
         if (d == D)
-            y_contrib<TJ, D>(J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cq, acc);
+            y_contrib<TJ, D>(J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cq, f, acc);
         else
             YDispatch<TJ, D + 1>::run(d, J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cq,
-                                      acc);
+                                      f, acc);
     }
 };
 template <int TJ>
 struct YDispatch<TJ, TJ + 1> {
     __device__ __forceinline__ static void run(int, int, int, int, int, int, int, int,
                                                const double2 *__restrict__, int, unsigned,
-                                               const double *__restrict__, const double *,
+                                               const double *__restrict__, const double *, double,
                                                double2 (&)[TJ / 2 + 1])
     {
     }
@@ -184,18 +185,12 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double2 acc[TJ / 2 + 1];
-#pragma unroll
-        for (int q = 0; q <= TJ / 2; ++q) acc[q] = make_double2(0.0, 0.0);
-        YDispatch<TJ, 0>::run(D, J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cqs[w],
-                              acc);
+        // the contribution's weight (multiplicity, beta, per-atom scale)
+        // rides on the row coefficient, so products accumulate into y
         const double bl = per_atom_beta ? beta[(size_t)asafe * nb + cl] : beta[cl];
         const double f = C->factor * bl * gs;
-#pragma unroll
-        for (int q = 0; q <= TJ / 2; ++q) {
-            y[q].x += f * acc[q].x;
-            y[q].y += f * acc[q].y;
-        }
+        YDispatch<TJ, 0>::run(D, J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cqs[w], f,
+                              y);
         // the next contribution overwrites the staged table
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
