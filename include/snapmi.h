@@ -157,6 +157,19 @@ int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const doubl
                   int per_atom_beta, const double *grad_energy, double *force, double *dE_pair,
                   void *stream);
 
+/* Virial of the pair derivatives of a previous snap_compute (dE_pair, dev
+ * double[npairs][3]): the derivative of the total energy with respect to a
+ * homogeneous strain r -> (I + eps) r,
+ *   virial[3a + b] = sum over pairs p = (i -> k) of dE_p[a] * r_ik[b]
+ * (r_ik by minimum image; eq. (snapforce2) gives dE_p per pair, Sec. IV keeps
+ * it, and this is the reduction such per-pair storage serves).  virial dev
+ * double[9] (row-major 3 x 3), virial_atom dev double[n][9] or NULL: the
+ * shares of the pairs of each atom i.  The sums are taken in a fixed order
+ * (deterministic).  pos, box, off, nbr as in snap_compute. */
+int snap_virial(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                const int *off, const int *nbr, const double *dE_pair, double *virial_atom,
+                double *virial, void *stream);
+
 /* Copy an internal per-atom array of the last call into dst (dev memory):
  * which = 0: U_j, which = 1: Y_j.  Layout: double[nhalf][n][2] (element-
  * major, re/im interleaved), elements in the order of snap_table(1). */

@@ -181,3 +181,23 @@ def snap(pos, box, twojmax, rcut, rfac0=0.99363, rmin0=0.0, switch_flag=1, wself
 
 def max_threads() -> int:
     return _load().oracle_max_threads()
+
+
+def virial(pos, box, off, nbr, dE):
+    """dE_total/d(strain) = sum over pairs p = (i -> k) of dE_p (x) r_ik, a
+    3x3 matrix W[a][b] = sum_p dE_p[a] r_ik[b] (r_ik by minimum image), and
+    the per-atom shares W_i (pairs of atom i).  Under r -> (I + eps) r the
+    energy changes by sum_ab W[a][b] eps[a][b] to first order."""
+    pos = np.asarray(pos, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    n = len(pos)
+    W_atom = np.zeros((n, 3, 3))
+    for i in range(n):
+        for p in range(off[i], off[i + 1]):
+            k = int(nbr[p])
+            r = pos[k] - pos[i]
+            for d in range(3):
+                if box[d] > 0.0:
+                    r[d] -= box[d] * np.round(r[d] / box[d])
+            W_atom[i] += np.outer(dE[p], r)
+    return W_atom.sum(0), W_atom

@@ -121,6 +121,7 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(w.U);
     (void)hipFree(w.Y);
     (void)hipFree(w.Epart);
+    (void)hipFree(w.vpart);
     (void)hipFree(w.dE);
     (void)hipFree(w.pair_atom);
     (void)hipFree(w.flag);
@@ -178,14 +179,17 @@ static int ensure_work(snap_ctx *c, int n, int np, hipStream_t s)
         (void)hipFree(w.U);
         (void)hipFree(w.Y);
         (void)hipFree(w.Epart);
+        (void)hipFree(w.vpart);
         w.U = w.Y = nullptr;
-        w.Epart = nullptr;
+        w.Epart = w.vpart = nullptr;
         c->cap_atoms = 0;
         HIP_TRY(hipMalloc((void **)&w.U, sizeof(double2) * (size_t)c->tab.nfullel * npad),
                 "alloc U");
         HIP_TRY(hipMalloc((void **)&w.Y, sizeof(double2) * nh * npad), "alloc Y");
         HIP_TRY(hipMalloc((void **)&w.Epart, sizeof(double) * c->tab.yrows.size() * npad),
                 "alloc Epart");
+        HIP_TRY(hipMalloc((void **)&w.vpart, sizeof(double) * 9 * (size_t)(npad / 256 + 1)),
+                "alloc virial partials");
         HIP_TRY(hipMemset(w.U, 0, sizeof(double2) * (size_t)c->tab.nfullel * npad), "clear U");
         HIP_TRY(hipMemset(w.Y, 0, sizeof(double2) * nh * npad), "clear Y");
         c->cap_atoms = npad;
@@ -571,6 +575,29 @@ int snap_sync_status(snap_ctx *c, void *stream)
     return SNAP_OK;
 }
 
+
+int snap_virial(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                const int *off, const int *nbr, const double *dE_pair, double *virial_atom,
+                double *virial, void *stream)
+{
+    // no reverse index or coefficients are read: nbr stands in for rev
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, nbr, nullptr, false);
+    if (st) return st;
+    if (!virial) return fail(SNAP_EINVAL, "NULL virial pointer");
+    if (npairs > 0 && !dE_pair) return fail(SNAP_EINVAL, "NULL dE_pair pointer");
+    if ((st = ensure_device(c))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_work(c, n > 0 ? n : 1, npairs > 0 ? npairs : 1, s))) return st;
+    const Geom g = make_geom(c, box);
+    if (n == 0) {
+        HIP_TRY(launch_virial(0, pos, off, nbr, g, dE_pair, nullptr, c->work.vpart, virial, s),
+                "virial launch");
+        return SNAP_OK;
+    }
+    HIP_TRY(launch_virial(n, pos, off, nbr, g, dE_pair, virial_atom, c->work.vpart, virial, s),
+            "virial launch");
+    return SNAP_OK;
+}
 
 // ---------------------------------------------------------------------------
 // learned surrogate

@@ -35,6 +35,7 @@ struct Work {
     double2 *U = nullptr, *Y = nullptr;
     double *dE = nullptr;
     double *Epart = nullptr;  // [nyrows][npad] per-row shares of the energy
+    double *vpart = nullptr;  // [npad/256 + 1][9] per-block virial sums
     int *pair_atom = nullptr;
     int *flag = nullptr;
     int npad = 0;
@@ -71,6 +72,12 @@ inline hipError_t launch_dedr(int twojmax, int dirs, int npairs, int npad, const
 
 hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *rev,
                          const double *dE, const double *Epart, double *energy, double *force,
+                         hipStream_t s);
+
+// virial W[a][b] = sum_p dE_p[a] r_ik[b]: per atom into watom[n][9] (if not
+// NULL), per block of 256 atoms into partial[ceil(n/256)][9], total into out[9]
+hipError_t launch_virial(int n, const double *pos, const int *off, const int *nbr, const Geom &g,
+                         const double *dE, double *watom, double *partial, double *out,
                          hipStream_t s);
 
 // dst[e][atom][re/im] = scale[e] * src[map[e] * npad + atom] for atom < n

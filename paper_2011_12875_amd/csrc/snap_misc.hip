@@ -152,6 +152,58 @@ __global__ __launch_bounds__(256) void k_gather(int n, int npad, int nrows,
     }
 }
 
+// ---------------------------------------------------------------------------
+// virial: W = dE_total/d(strain) = sum_p dE_p (x) r_ik (lane per atom), per
+// atom (optional) and per block of 256 atoms, summed in a fixed order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_virial(int n, const double *__restrict__ pos,
+                                                const int *__restrict__ off,
+                                                const int *__restrict__ nbr, Geom g,
+                                                const double *__restrict__ dE,
+                                                double *__restrict__ watom,
+                                                double *__restrict__ partial)
+{
+    __shared__ double red[9][256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = 0.0;
+    if (i < n) {
+        const int pe = off[i + 1];
+        for (int p = off[i]; p < pe; ++p) {
+            double rv[3];
+            min_image(pos, i, nbr[p], g, rv);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) w[3 * a + b] += dE[3 * (size_t)p + a] * rv[b];
+        }
+        if (watom)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) watom[9 * (size_t)i + k] = w[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[k][threadIdx.x] = w[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) partial[9 * (size_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_virial_sum(int nblk, const double *__restrict__ partial,
+                             double *__restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= 9) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[9 * (size_t)b + k];
+    out[k] = s;
+}
+
 // dst[e][i] = scale[e] * src[map[e] * npad + i] (map, scale optional)
 __global__ void k_unscale(int n, int npad, int nhalf, const double2 *__restrict__ src,
                           const int *__restrict__ map, const double *__restrict__ scale,
@@ -199,6 +251,21 @@ hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *
     constexpr int apb = 256 / kGatherLanes;  // atoms per block
     hipLaunchKernelGGL(k_gather, dim3((n + apb - 1) / apb), dim3(256), 0, s, n, npad, nrows, off,
                        rev, dE, Epart, energy, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_virial(int n, const double *pos, const int *off, const int *nbr, const Geom &g,
+                         const double *dE, double *watom, double *partial, double *out,
+                         hipStream_t s)
+{
+    const int nblk = (n + 255) / 256;
+    if (nblk > 0) {
+        hipLaunchKernelGGL(k_virial, dim3(nblk), dim3(256), 0, s, n, pos, off, nbr, g, dE, watom,
+                           partial);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_virial_sum, dim3(1), dim3(64), 0, s, nblk, partial, out);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_n
            "snap_stage_times", "snap_sync_status", "snap_last_error",
            "snap_mlp_nparams", "snap_mlp_workspace", "snap_mlp_forward", "snap_mlp_grad",
            "snap_adam_step", "snap_jacobian", "snap_jacobian_forces", "snap_jacobian_adjoint",
-           "snap_fit_residuals"]
+           "snap_fit_residuals", "snap_virial"]
 
 
 class SnapError(RuntimeError):
@@ -81,6 +81,7 @@ def load():
         "snap_jacobian_forces": (i, [i, i, i, vp, vp, vp, vp, vp, vp, vp]),
         "snap_jacobian_adjoint": (i, [i, i, i, vp, vp, vp, vp, vp, vp]),
         "snap_fit_residuals": (i, [i, vp, vp, vp, vp, d, d, vp, vp, vp, vp]),
+        "snap_virial": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -308,6 +309,22 @@ class SnapPotential:
             self._ptr(nl.rev), self._ptr(bispectrum), self._ptr(jac), self._stream()))
         self._fwd_token += 1
         return bispectrum, jac
+
+    def virial(self, pos, box, nl, dE, per_atom=False):
+        """W[a][b] = sum_p dE_p[a] r_ik[b] (3x3) from the pair derivatives of
+        compute(..., pair_derivs=True); with per_atom also W_i [n, 3, 3]."""
+        import torch
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+        n = pos.shape[0]
+        assert nl.n == n and dE.dtype == torch.float64 and dE.is_contiguous()
+        boxa = (ctypes.c_double * 3)(*[float(x) for x in box])
+        W = torch.empty(9, dtype=torch.float64, device=pos.device)
+        Wa = torch.empty((n, 9), dtype=torch.float64, device=pos.device) if per_atom else None
+        _check(load().snap_virial(self._ctx, n, nl.npairs, self._ptr(pos), boxa,
+                                  self._ptr(nl.off), self._ptr(nl.nbr), self._ptr(dE),
+                                  self._ptr(Wa), self._ptr(W), self._stream()))
+        W = W.reshape(3, 3)
+        return (W, Wa.reshape(n, 3, 3)) if per_atom else W
 
     def workspace(self, which, n):
         """True U_j (which=0) or Y_j (which=1) of the last call: [nhalf, n] complex."""

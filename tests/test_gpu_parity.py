@@ -241,3 +241,22 @@ def test_backward_matches_weighted_forces():
     _check_energy(E.cpu().numpy(), ob["E"])
     assert np.abs(F.cpu().numpy() - o["F"]).max() <= F_ABS
     assert np.abs(B.cpu().numpy() - ob["B"]).max() <= E_REL * max(1.0, np.abs(ob["B"]).max())
+
+
+@pytest.mark.parametrize("name", ["bcc128_2j4", "bcc2000_2j8"])
+def test_virial_matches_oracle(name):
+    """W = sum_p dE_p (x) r_ik from the GPU pair derivatives against the
+    oracle's (its own dE and minimum image); per-atom shares sum to W; W is
+    symmetric (rotational invariance)."""
+    pos, box, beta, tj = _full(name)
+    g = _run(pos, box, beta, tj)
+    W, Wa = g["pot"].virial(g["tpos"], box, g["nl"], _torch().as_tensor(g["dE"], device="cuda"),
+                            per_atom=True)
+    W, Wa = W.cpu().numpy(), Wa.cpu().numpy()
+    o = oracle.snap(pos, box, tj, wl.RCUT, beta=beta)
+    Wo, Wao = oracle.virial(pos, box, o["off"], o["nbr"], o["dE"])
+    scale = np.abs(Wao).max()
+    assert np.abs(Wa - Wao).max() <= 1e-10 * scale
+    assert np.abs(W - Wo).max() <= 1e-10 * np.abs(Wo).max()
+    assert np.abs(Wa.sum(0) - W).max() <= 1e-12 * np.abs(W).max() * len(pos)
+    assert np.abs(W - W.T).max() <= 1e-9 * np.abs(W).max()
