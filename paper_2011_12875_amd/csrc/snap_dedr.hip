@@ -36,11 +36,18 @@ __device__ __forceinline__ void load_level(double2 (&y)[TJ + 1], int J, int eb,
 // (size Jn + 1 at half index ebn, Jn < 0 for none) are issued before the
 // compiler fence that closes the level, so that their latency overlaps the
 // next level's recursion.
+// Above 2J = 10 the levels run in a loop over J (straight-line code would be
+// too long); there both the look-ahead loads and the per-element pins cost
+// more registers than the loop has, so the level loads its own Y~ instead.
+template <int TJ>
+constexpr bool kDedrStraight = TJ <= 10;
+
 template <int TJ, int ND, bool DZ>
 __device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ, ND> &st,
                                            double2 a, double2 b, const double2 (&da)[ND],
                                            const double2 (&db)[ND],
-                                           const double2 *__restrict__ Y, unsigned i, int npad)
+                                           const double2 *__restrict__ Y, unsigned i, int npad,
+                                           int eb = 0)
 {
 #pragma unroll
     for (int p = TJ; p >= 0; --p)
@@ -84,21 +91,28 @@ __device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ,
             st.col[p] = make_double2(nr, ni);
 #pragma unroll
             for (int d = 0; d < ND; ++d) st.dcol[d][p] = make_double2(dnr[d], dni[d]);
-            // close each element's live range here (without, the level's
-            // products are interleaved across elements and spill at 2J = 8)
-            pin(st.col[p]);
+            if constexpr (kDedrStraight<TJ>) {
+                // close each element's live range here (without, the level's
+                // products are interleaved across elements and spill at 2J = 8)
+                pin(st.col[p]);
 #pragma unroll
-            for (int d = 0; d < ND; ++d) pin(st.dcol[d][p]);
+                for (int d = 0; d < ND; ++d) pin(st.dcol[d][p]);
+            }
         }
 #pragma unroll
     for (int p = 0; p <= TJ; ++p)
         if (p <= J) {
-            const double2 y = st.y[p];
+            double2 y;
+            if constexpr (kDedrStraight<TJ>)
+                y = st.y[p];
+            else
+                y = load_row(Y, (size_t)(eb + p), npad, i * 16u);
             st.S0 += y.x * st.col[p].x + y.y * st.col[p].y;
 #pragma unroll
             for (int d = 0; d < ND; ++d) st.S[d] += y.x * st.dcol[d][p].x + y.y * st.dcol[d][p].y;
         }
-    if (Jn >= 0) load_level<TJ>(st.y, Jn, ebn, Y, i, npad);
+    if constexpr (kDedrStraight<TJ>)
+        if (Jn >= 0) load_level<TJ>(st.y, Jn, ebn, Y, i, npad);
 #pragma unroll
     for (int p = 0; p <= TJ; ++p)
         if (p <= J) {
@@ -131,8 +145,7 @@ __device__ __forceinline__ void dedr_column(DedrState<TJ, ND> &st, double2 a, do
     constexpr int QN = Q + 1;
     constexpr int JN = (2 * QN <= TJ) ? 2 * QN : -1;
     constexpr int EBN = (JN >= 0) ? hbase_of(2 * QN) + QN * (2 * QN + 1) : 0;
-    constexpr bool kFull = TJ <= 10;  // straight-line code up to 2J = 10
-    if constexpr (kFull) {
+    if constexpr (kDedrStraight<TJ>) {
 #pragma unroll
         for (int J = J0; J <= TJ; ++J) {
             const int Jn = (J < TJ) ? J + 1 : JN;
@@ -158,10 +171,7 @@ __device__ __forceinline__ void dedr_column(DedrState<TJ, ND> &st, double2 a, do
 #pragma unroll 1
         for (int J = J0; J <= TJ; ++J) {
             const int ebnext = eb + (J + 1) * (J / 2 + 1) + Q;  // half index of (J+1, 0, Q)
-            if (J < TJ)
-                dedr_level<TJ, ND, false>(J, J + 1, ebnext, st, a, b, da, db, Y, i, npad);
-            else
-                dedr_level<TJ, ND, false>(J, JN, EBN, st, a, b, da, db, Y, i, npad);
+            dedr_level<TJ, ND, false>(J, -1, 0, st, a, b, da, db, Y, i, npad, eb);
             if (J == 2 * Q + 1 && 2 * Q + 2 <= TJ) {
                 mirror_seed<TJ, Q>(st.col, st.seed);
 #pragma unroll
@@ -250,7 +260,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
 #pragma unroll
         for (int d = 0; d < ND; ++d) st.dseed[d][p] = make_double2(0.0, 0.0);
     }
-    if constexpr (TJ >= 1) load_level<TJ>(st.y, 1, hbase_of(1), Y, (unsigned)i, npad);
+    if constexpr (TJ >= 1 && kDedrStraight<TJ>)
+        load_level<TJ>(st.y, 1, hbase_of(1), Y, (unsigned)i, npad);
     st.S0 = y00;  // J = 0: poly = 1, dpoly = 0
     DedrColumns<TJ, ND, 0>::run(st, pg.a, pg.b, da, db, Y, (unsigned)i, npad);
     if (valid) {
