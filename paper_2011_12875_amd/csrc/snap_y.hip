@@ -131,12 +131,14 @@ struct YDispatch<TJ, TJ + 1> {
 
 // Workgroup = (row (J, p) of Y, block of 64 atoms); its contributions are
 // split over four wavefronts and reduced in LDS.  Workgroup u runs on XCD
-// u mod 8 and takes atom block 8 floor(s / nrows) + (u mod 8), row
-// s mod nrows, s = floor(u / 8): every XCD owns the blocks congruent to it
-// mod 8 (atom blocks padded to a multiple of 8) and walks them one block at
-// a time, all rows of a block before the next, so its L2 holds the U of a
-// few blocks at any time, whatever the system size.  Also writes the row's
-// share of the energy, (1/3) sum_q Re(Y~ conj(U~)), to Epart.
+// u mod 8, which owns the atom blocks congruent to it mod 8 (blocks padded
+// to a multiple of 8).  An XCD walks its blocks in groups of kYGroup: within
+// a group row-major (the rows are sorted by decreasing cost, so the heavy
+// rows of the group start first), group after group, so its L2 holds the U
+// of kYGroup blocks (1.2 MB at 2J = 8) whatever the system size.  Also
+// writes the row's share of the energy, (1/3) sum_q Re(Y~ conj(U~)), to
+// Epart.
+constexpr int kYGroup = 4;
 template <int TJ>
 __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_compute_y(
     int n, int npad, int nblk8, const double2 *__restrict__ U, double2 *__restrict__ Y,
@@ -149,9 +151,13 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
     __shared__ double cqs[kYWaves][kCqMax];
     const int unit = blockIdx.x;
     const int nrows = (int)gridDim.x / nblk8;
-    const int sx = unit >> 3;
-    const int rix = sx % nrows;
-    const int blk = (sx / nrows) * 8 + (unit & 7);
+    const int nbx = nblk8 >> 3;  // blocks per XCD
+    const int sx = unit >> 3;    // slot within the XCD
+    const int grp = sx / (kYGroup * nrows);
+    const int gsz = (grp < nbx / kYGroup) ? kYGroup : nbx - grp * kYGroup;
+    const int t = sx - grp * kYGroup * nrows;
+    const int rix = t / gsz;
+    const int blk = (grp * kYGroup + (t - rix * gsz)) * 8 + (unit & 7);
     if (blk * 64 >= n) return;  // padding block (uniform for the workgroup)
     // the wavefront index is uniform within a wavefront; say so, or every
     // value derived from it is treated as divergent (vector loads, masks)
