@@ -1,26 +1,30 @@
-// snap_kernels.hip -- FP64 SNAP kernels for gfx950 (MI355X).
+// snap_device.hpp -- device helpers shared by the FP64 SNAP kernels for gfx950
+// (MI355X).
 //
 // Stages (arXiv 2011.12875, Sec. IV Listing 5 with the GPU refinements of
 // Sec. VI):
-//   k_compute_u  eq. (u): one lane per (atom, neighbour) pair runs the
-//                hyperspherical-harmonic recursion eq. (hysphrecur) for the
-//                stored half of every u_j (Sec. VI), column by column in
-//                registers; the per-atom sum U_j is reduced through LDS in a
-//                fixed order (no atomics, bit-reproducible).
-//   k_compute_y  eq. (y): one lane per atom (64 consecutive atoms per
-//                wavefront, like the AoSoA layout of Sec. VI), all lanes
-//                running the same Clebsch-Gordan contraction program, so
-//                coefficients and indices are wavefront-uniform (scalar
-//                loads); rows (j, p) of Y are split over four wavefronts and
-//                reduced in LDS.
-//   k_bispectrum eq. (z) and eq. (snapatomenergy), on request.
+//   k_compute_u  eq. (u) (snap_u.hip): lanes walk (atom, neighbour) pairs,
+//                two pairs of one atom per lane, one workgroup per column of
+//                the stored half of u_j (Sec. VI) and group of four atoms;
+//                the recursion eq. (hysphrecur) runs in registers and the
+//                per-atom sum U_j is reduced through LDS in a fixed order (no
+//                atomics, bit-reproducible).
+//   k_compute_y  eq. (y) (snap_y.hip): one lane per atom (64 consecutive
+//                atoms per wavefront, like the AoSoA layout of Sec. VI), all
+//                lanes running the same Clebsch-Gordan contraction program,
+//                so coefficients and indices are wavefront-uniform; rows
+//                (j, p) of Y are split over four wavefronts and reduced in
+//                LDS.
+//   k_bispectrum eq. (z) and eq. (snapatomenergy), on request (snap_misc.hip;
+//                U staged in LDS for small 2J).
 //   k_dedr       eq. (snapforce2) fused with the derivative recursion
-//                ("compute_fused_dE", Sec. VI): one lane per pair (and per
-//                direction when split, as Sec. VI splits x, y, z), u and du
+//                ("compute_fused_dE", Sec. VI) (snap_dedr.hip): one lane per
+//                pair and direction (Sec. VI splits x, y, z too), u and du
 //                recomputed in registers and contracted with Y on the fly.
 //   k_gather     update_forces: F_i = sum_out dE_p - sum_out dE_rev(p), a
 //                deterministic gather through the reverse-pair index; also the
 //                energy E_i = (1/3) Re sum_j Y_j : U_j^* (B is cubic in U).
+//   k_virial     sum_p dE_p (x) r_ik per atom and in total.
 //
 // Conventions: twice-integer J, row p, column q, stored half q <= J/2.
 // The recursion runs on the polynomial coefficients poly^J_{pq} = u^J_{pq}/N
@@ -28,8 +32,9 @@
 //   poly^J_{pq} = a* poly^{J-1}_{pq} - b* poly^{J-1}_{p-1,q}
 // with unit weights, and the mirror rule
 //   poly^J_{J-p,J-q} = (-1)^(p-q) conj(poly^J_{pq}).
-// Per-atom arrays are element-major X[e * npad + atom] of double2 (re, im)
-// and hold the scaled values U~ = U/N and Y~ = w N Y (w: half-sum weight).
+// Per-atom arrays are element-major X[e * npad + atom] of double2 (re, im):
+// U holds full (J+1) x (J+1) matrices of true values, Y the stored half of
+// the scaled Y~ = w N Y (w: half-sum weight).
 #pragma once
 #include <hip/hip_runtime.h>
 
