@@ -131,23 +131,25 @@ void build_tables(int tj, Tables &t)
         std::vector<int> cq_at((tj + 1) * (tj + 1) * (tj + 1), -1);
         auto cqix = [&](int a, int b, int c) -> int & { return cq_at[(a * (tj + 1) + b) * (tj + 1) + c]; };
         for (int J = 0; J <= tj; ++J)
-            for (int p = 0; p <= J; ++p) {
+            for (int p = 0; p <= J; p += y_unit_rows(tj)) {
+                const int two = y_unit_rows(tj) == 2 && p + 1 <= J;
                 PendingC pr;
                 pr.row.J = J;
                 pr.row.p = p;
                 pr.row.nq = J / 2 + 1;
                 pr.row.ebase = t.half_index(J, p, 0);
                 pr.row.frow = t.full_index(J, p, 0);
-                for (int q = 0; q < 8; ++q) {
-                    if (q < pr.row.nq) {
-                        const int e = t.half_index(J, p, q);
-                        pr.row.oscale[q] = t.whalf[e] * t.norm[e];
-                        pr.row.einv[q] = 1.0 / t.norm[e];
-                    } else {
-                        pr.row.oscale[q] = pr.row.einv[q] = 0.0;
+                pr.row.two = two;
+                for (int r = 0; r < 2; ++r)
+                    for (int q = 0; q < 8; ++q) {
+                        if (q < pr.row.nq && r <= two) {
+                            const int e = t.half_index(J, p + r, q);
+                            pr.row.oscale[r][q] = t.whalf[e] * t.norm[e];
+                            pr.row.einv[r][q] = 1.0 / t.norm[e];
+                        } else {
+                            pr.row.oscale[r][q] = pr.row.einv[r][q] = 0.0;
+                        }
                     }
-                }
-                const int M = 2 * p - J;
                 for (int a = 0; a <= tj; ++a)
                     for (int b = 0; b <= a; ++b) {
                         if (J < a - b || J > a + b || (a + b + J) % 2) continue;
@@ -159,21 +161,23 @@ void build_tables(int tj, Tables &t)
                         c.d = (a + b - J) / 2;
                         c.l = cix(s3[1], s3[0], s3[2]);
                         c.factor = (double)((a == J) + (b == J) + 1) * (double)(s3[2] + 1) / (double)(J + 1);
-                        // valid rows: p2 = p - p1 + d in [0, b]
+                        // valid rows of row p + r: p2 = p + r - p1 + d in [0, b]
                         c.p1lo = std::max(0, p + c.d - b);
-                        c.p1hi = std::min(a, p + c.d);
+                        c.p1hi = std::min(a, p + two + c.d);
                         if (c.p1lo > c.p1hi) continue;
                         c.cp_off = (int)t.ycp.size();
-                        for (int p1 = c.p1lo; p1 <= c.p1hi; ++p1) {
-                            const int M1 = 2 * p1 - a;
-                            t.ycp.push_back(cg(a, M1, b, M - M1, J));
-                        }
+                        for (int p1 = c.p1lo; p1 <= c.p1hi; ++p1)
+                            for (int r = 0; r < 2; ++r) {
+                                const int p2 = p + r - p1 + c.d;
+                                const bool ok = r <= two && p2 >= 0 && p2 <= b;
+                                t.ycp.push_back(ok ? cg(a, 2 * p1 - a, b, 2 * (p + r) - J - (2 * p1 - a), J) : 0.0);
+                            }
                         if (cqix(a, b, J) < 0) {
                             cqix(a, b, J) = (int)t.ycq.size();
                             for (int q = 0; q <= J / 2; ++q)
-                                for (int q1 = 0; q1 <= a; ++q1) {
+                                for (int q1 = 0; q1 <= tj; ++q1) {
                                     const int N1 = 2 * q1 - a, N2 = (2 * q - J) - N1;
-                                    t.ycq.push_back(std::abs(N2) <= b ? cg(a, N1, b, N2, J) : 0.0);
+                                    t.ycq.push_back(q1 <= a && std::abs(N2) <= b ? cg(a, N1, b, N2, J) : 0.0);
                                 }
                         }
                         c.cq_off = cqix(a, b, J);
@@ -183,10 +187,15 @@ void build_tables(int tj, Tables &t)
                                 const int q2 = q - q1 + c.d;
                                 if (q2 >= 0 && q2 <= b) ++terms;
                             }
+                        // the algorithmic work counts each row's own p1 range
+                        for (int r = 0; r <= two; ++r) {
+                            const int lo = std::max(0, p + r + c.d - b), hi = std::min(a, p + r + c.d);
+                            if (lo > hi) continue;
+                            t.yterms += (long)(hi - lo + 1) * terms;
+                            t.ypartials += (long)(hi - lo + 1) * (J / 2 + 1);
+                        }
                         const int rowsn = c.p1hi - c.p1lo + 1;
-                        c.cost = rowsn * (6 * terms + 2 * (a + b + 2) + 4 * (J / 2 + 1)) + 16;
-                        t.yterms += (long)rowsn * terms;
-                        t.ypartials += (long)rowsn * (J / 2 + 1);
+                        c.cost = rowsn * ((1 + two) * (6 * terms + 4 * (J / 2 + 1)) + 2 * (a + b + 2)) + 16;
                         pr.cs.push_back(c);
                     }
                 // longest-processing-time assignment to the waves

@@ -55,25 +55,35 @@ struct BItem {
 //   Z(p, q) = sum_{p1} cp[p1] sum_{q1} cq[q][q1] U^J1(p1, q1) U^J2(p2, q2),
 //   p2 = p - p1 + d, q2 = q - q1 + d, d = (J1 + J2 - J)/2,
 // with true (unscaled) U values; cp and cq are Clebsch-Gordan coefficients.
+// A unit of compute_Y holds the rows p and p + 1 of one J (p alone for the
+// last row of an even J, and every row when 2J_max > 9): row p + 1 pairs U^J1 row p1 with the U^J2 row
+// that row p pairs with p1 - 1, so each loaded row serves both.  The p1
+// range of a contribution is the union of the two rows' ranges, and cp
+// holds two values per p1 (zero where that row has no valid p2).
 struct YContrib {
     int32_t j1, j2, d, l;  // input ranks, offset d, canonical component l
     double factor;         // multiplicity * (J_max + 1)/(J + 1)
-    int32_t p1lo, p1hi;    // rows p1 of U^J1 with a valid p2 (inclusive)
-    int32_t cp_off;        // cp of p1 at cp_off + (p1 - p1lo)
-    int32_t cq_off;        // cq[q][q1] at cq_off + q * (j1 + 1) + q1, q < nq
+    int32_t p1lo, p1hi;    // rows p1 of U^J1 used by either row (inclusive)
+    int32_t cp_off;        // cp of (p1, row r) at cp_off + 2 (p1 - p1lo) + r
+    int32_t cq_off;        // cq[q][q1] at cq_off + q * (2J_max + 1) + q1, q < nq (zero for q1 > j1)
     int32_t cost;          // estimated lane operations
     int32_t pad;
 };
 
-// A row (J, p) of Y in the row-blocked program, split over the waves of one
-// workgroup: contributions of wave w are cb[w] .. cb[w+1]-1.
+// Rows per unit: two while the second row's registers fit (2J_max <= 9),
+// one above.
+constexpr int y_unit_rows(int twojmax) { return twojmax <= 9 ? 2 : 1; }
+
+// A unit (rows p, p + 1 of J) of Y, split over the waves of one workgroup:
+// contributions of wave w are cb[w] .. cb[w+1]-1.
 struct YRowC {
-    int32_t J, p, nq, ebase;
+    int32_t J, p, nq, ebase;  // ebase: half index of (J, p, 0)
     int32_t cb[kYWaves + 1];
-    int32_t cost;            // busiest wave
-    int32_t frow;            // full index of (J, p, 0)
-    double oscale[8];        // w N of the outputs (J, p, q): Y~ = w N Y
-    double einv[8];          // 1/N of the outputs: Re(Y~ conj(U)) / N = w Re(Y conj(U))
+    int32_t cost;             // busiest wave
+    int32_t frow;             // full index of (J, p, 0)
+    int32_t two;              // 1 if the unit also holds row p + 1
+    double oscale[2][8];      // w N of the outputs (J, p + r, q): Y~ = w N Y
+    double einv[2][8];        // 1/N of the outputs: Re(Y~ conj(U)) / N = w Re(Y conj(U))
 };
 
 struct Tables {

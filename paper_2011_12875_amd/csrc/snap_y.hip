@@ -9,46 +9,29 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // compute_Y (adjoint of eq. (y)) -- lanes are atoms
 // ---------------------------------------------------------------------------
-constexpr int kYMaxQ = 8;      // J/2 + 1 for J <= 14
-constexpr int kCqMax = 8 * 15; // nq * (J1 + 1) for J, J1 <= 14
-
-constexpr int fbase_of(int J)  // first full element of rank J (blocks of (J+1)^2)
-{
-    int s = 0;
-    for (int k = 0; k < J; ++k) s += (k + 1) * (k + 1);
-    return s;
-}
+// first full element of rank J (blocks of (J+1)^2)
 __device__ __forceinline__ int fbase_rt(int J)
 {
     return (J * (J + 1) * (2 * J + 1)) / 6;  // sum_{k=1}^{J} k^2
 }
-__device__ __forceinline__ int hbase_rt(int J)
-{
-    // sum_{k<J} (k+1)(k/2+1), closed form per parity
-    const int m = J / 2;
-    // pairs (2i, 2i+1) for i < m contribute (2i+1)(i+1) + (2i+2)(i+1)
-    int s = 0;
-    for (int i = 0; i < m; ++i) s += (4 * i + 3) * (i + 1);
-    if (J & 1) s += (2 * m + 1) * (m + 1);
-    return s;
-}
-
 // Full row px of U^Jx (true values), elements f = fbase(Jx) + px (Jx+1) + q:
 // one buffer descriptor for the row (scalar registers), the element offset
-// in the scalar offset, the atom in the lane offset.  Entries q > Jx are
-// zero, so that products with them vanish.
+// in the scalar offset, the atom in the lane offset.  Entries q > Jx, and
+// the whole row when it is not valid, are zero, so that products with them
+// vanish.
 template <int TJ>
-__device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int px,
+__device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int px, bool valid,
                                               const double2 *__restrict__ U, int npad,
                                               unsigned voff)
 {
-    const double2 *base = U + (size_t)(fbase_rt(Jx) + px * (Jx + 1)) * (size_t)npad;
+    const int pv = valid ? px : 0;
+    const double2 *base = U + (size_t)(fbase_rt(Jx) + pv * (Jx + 1)) * (size_t)npad;
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)base, (short)0, (Jx + 1) * npad * 16, 0x00020000);
 #pragma unroll
     for (int q = 0; q <= TJ; ++q) {
         r[q] = make_double2(0.0, 0.0);
-        if (q <= Jx) {
+        if (valid && q <= Jx) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, q * npad * 16, 0);
             r[q] = make_double2(
                 __builtin_bit_cast(double, (unsigned long long)v[0] | ((unsigned long long)v[1] << 32)),
@@ -57,87 +40,138 @@ __device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int 
     }
 }
 
-// One contribution (J1, J2 -> J) to row p of Y, accumulated into acc[q].
+// acc[q] += cpv sum_{q1} cq[q][q1] r1[q1] r2[q - q1 + D] for q < nq.
 // q2 = q - q1 + D is a compile-time index into the second row.  Every
 // (q, q1) with q1, q2 in [0, 2J_max] is evaluated without a test: rows are
-// zero beyond J1 and J2 and the staged column coefficients beyond J1, so
-// the terms outside the Clebsch-Gordan range add exact zeros (about 6 % of
-// the products at 2J = 8); only the row index q < nq is tested, once per q.
-// The coefficients sit at compile-time offsets cq[q (2J_max + 1) + q1].
+// zero beyond J1 and J2 and the coefficient table beyond J1, so the terms
+// outside the Clebsch-Gordan range add exact zeros; only the row index
+// q < nq is tested, once per q.  The coefficients are uniform over the
+// wavefront and sit at compile-time offsets cq[q (2J_max + 1) + q1] of the
+// global table, so they are read with scalar loads and enter the products
+// as scalar operands (no LDS staging, no vector registers).
+template <int TJ, int D>
+__device__ __forceinline__ void row_product(const double2 (&r1)[TJ + 1],
+                                            const double2 (&r2)[TJ + 1], const double *__restrict__ cq,
+                                            double cpv, int nq, double2 (&acc)[TJ / 2 + 1])
+{
+#pragma unroll
+    for (int q = 0; q <= TJ / 2; ++q)
+        if (q < nq) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int q1 = 0; q1 <= TJ; ++q1) {
+                const int q2 = q - q1 + D;  // compile-time
+                if (q2 >= 0 && q2 <= TJ) {
+                    const double c = cq[q * (TJ + 1) + q1];
+                    const double2 x = r1[q1], y = r2[q2 < 0 ? 0 : (q2 > TJ ? TJ : q2)];
+                    const double pr = x.x * y.x - x.y * y.y;
+                    const double pi = x.x * y.y + x.y * y.x;
+                    sr += c * pr;
+                    si += c * pi;
+                }
+            }
+            acc[q].x += cpv * sr;
+            acc[q].y += cpv * si;
+        }
+}
+
+// One contribution (J1, J2 -> J) to the rows p and p + 1 of Y, accumulated
+// into acc0 and acc1.  Row p pairs U^J1 row p1 with U^J2 row p - p1 + D,
+// row p + 1 pairs it with p + 1 - p1 + D: the row that row p used at
+// p1 - 1.  The rows therefore form one chain, U^J2 row p + 1 - p1lo + D,
+// U^J1 row p1lo, U^J2 row p - p1lo + D, U^J1 row p1lo + 1, ..., in which
+// every two neighbours make one row product (alternately of row p + 1 and
+// row p): each step loads one row into the slot of its rank and multiplies
+// the two slots.  Rows outside [0, J2] (at the two ends of the union range)
+// are zero, and so are their coefficients.
 template <int TJ, int D>
 __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, int cp_off, int p,
-                                          int nq, const double2 *__restrict__ U, int npad,
-                                          unsigned voff, const double *__restrict__ cpt,
-                                          const double *cq, double f, double2 (&acc)[TJ / 2 + 1])
+                                          int nq, int two, const double2 *__restrict__ U,
+                                          int npad, unsigned voff,
+                                          const double *__restrict__ cpt, const double *__restrict__ cq,
+                                          double f, double2 *ysum, int lane)
 {
+    constexpr bool kTwo = y_unit_rows(TJ) == 2;
+    // the contribution's own sums: kept local, so that no accumulator is
+    // live across the dispatch over D (each branch would hold its own copy)
+    double2 acc0[TJ / 2 + 1], acc1[TJ / 2 + 1];
+#pragma unroll
+    for (int q = 0; q <= TJ / 2; ++q) {
+        acc0[q] = make_double2(0.0, 0.0);
+        acc1[q] = make_double2(0.0, 0.0);
+    }
+    double2 s1[TJ + 1], s2[TJ + 1];  // the current rows of U^J1 and U^J2
+    if (kTwo && two) {
+        const int p2 = p + 1 - p1lo + D;
+        load_full_row<TJ>(s2, J2, p2, p2 <= J2, U, npad, voff);
+    }
     for (int p1 = p1lo; p1 <= p1hi; ++p1) {
-        const int p2 = p - p1 + D;
         // re-derive the bounds in every iteration: hoisted out of the loop,
         // the guard compares below would each hold a scalar register for the
         // whole loop and spill
         int j1 = J1, j2 = J2, qn = nq;
         asm volatile("" : "+s"(j1), "+s"(j2), "+s"(qn));
-        double2 r1[TJ + 1], r2[TJ + 1];
-        load_full_row<TJ>(r1, j1, p1, U, npad, voff);
-        load_full_row<TJ>(r2, j2, p2, U, npad, voff);
-        const double cpv = f * cpt[cp_off + (p1 - p1lo)];
-#pragma unroll
-        for (int q = 0; q <= TJ / 2; ++q)
-            if (q < qn) {
-                double sr = 0.0, si = 0.0;
-#pragma unroll
-                for (int q1 = 0; q1 <= TJ; ++q1) {
-                    const int q2 = q - q1 + D;  // compile-time
-                    if (q2 >= 0 && q2 <= TJ) {
-                        const double c = cq[q * (TJ + 1) + q1];
-                        const double2 x = r1[q1], y = r2[q2 < 0 ? 0 : (q2 > TJ ? TJ : q2)];
-                        const double pr = x.x * y.x - x.y * y.y;
-                        const double pi = x.x * y.y + x.y * y.x;
-                        sr += c * pr;
-                        si += c * pi;
-                    }
-                }
-                acc[q].x += cpv * sr;
-                acc[q].y += cpv * si;
-            }
+        const double *cp = cpt + cp_off + 2 * (p1 - p1lo);
+        load_full_row<TJ>(s1, j1, p1, true, U, npad, voff);
+        if (kTwo && two) row_product<TJ, D>(s1, s2, cq, f * cp[1], qn, acc1);
+        const int p2 = p - p1 + D;
+        load_full_row<TJ>(s2, j2, p2, p2 >= 0, U, npad, voff);
+        row_product<TJ, D>(s1, s2, cq, f * cp[0], qn, acc0);
     }
+    // ysum[(r (J_max/2 + 1) + q) 64 + lane]: this lane's entries only
+#pragma unroll
+    for (int q = 0; q <= TJ / 2; ++q)
+        if (q < nq) {
+            double2 *a = ysum + q * 64 + lane;
+            a->x += acc0[q].x;
+            a->y += acc0[q].y;
+            if constexpr (kTwo) {
+                double2 *b = ysum + ((TJ / 2 + 1) + q) * 64 + lane;
+                b->x += acc1[q].x;
+                b->y += acc1[q].y;
+            }
+        }
 }
 
 template <int TJ, int D>
 struct YDispatch {
     __device__ __forceinline__ static void run(int d, int J1, int J2, int p1lo, int p1hi,
-                                               int cp_off, int p, int nq,
+                                               int cp_off, int p, int nq, int two,
                                                const double2 *__restrict__ U, int npad,
                                                unsigned voff, const double *__restrict__ cpt,
-                                               const double *cq, double f,
-                                               double2 (&acc)[TJ / 2 + 1])
+                                               const double *__restrict__ cq, double f, double2 *ysum,
+                                               int lane)
     {
         if (d == D)
-            y_contrib<TJ, D>(J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cq, f, acc);
+            y_contrib<TJ, D>(J1, J2, p1lo, p1hi, cp_off, p, nq, two, U, npad, voff, cpt, cq, f,
+                             ysum, lane);
         else
-            YDispatch<TJ, D + 1>::run(d, J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cq,
-                                      f, acc);
+            YDispatch<TJ, D + 1>::run(d, J1, J2, p1lo, p1hi, cp_off, p, nq, two, U, npad, voff,
+                                      cpt, cq, f, ysum, lane);
     }
 };
 template <int TJ>
 struct YDispatch<TJ, TJ + 1> {
-    __device__ __forceinline__ static void run(int, int, int, int, int, int, int, int,
+    __device__ __forceinline__ static void run(int, int, int, int, int, int, int, int, int,
                                                const double2 *__restrict__, int, unsigned,
                                                const double *__restrict__, const double *, double,
-                                               double2 (&)[TJ / 2 + 1])
+                                               double2 *, int)
     {
     }
 };
 
-// Workgroup = (row (J, p) of Y, block of 64 atoms); its contributions are
-// split over four wavefronts and reduced in LDS.  Workgroup u runs on XCD
-// u mod 8, which owns the atom blocks congruent to it mod 8 (blocks padded
-// to a multiple of 8).  An XCD walks its blocks in groups of kYGroup: within
-// a group row-major (the rows are sorted by decreasing cost, so the heavy
-// rows of the group start first), group after group, so its L2 holds the U
-// of kYGroup blocks (1.2 MB at 2J = 8) whatever the system size.  Also
-// writes the row's share of the energy, (1/3) sum_q Re(Y~ conj(U~)), to
-// Epart.
+// Workgroup = (unit of rows p, p + 1 of J, block of 64 atoms); its
+// contributions are split over four wavefronts, each of which adds its
+// contributions' sums into its own LDS slice (an accumulator held in
+// registers across the dispatch over D would be duplicated in every
+// branch), and the slices are reduced at the end.
+// Workgroup u runs on XCD u mod 8, which owns the atom blocks congruent to
+// it mod 8 (blocks padded to a multiple of 8).  An XCD walks its blocks in
+// groups of kYGroup: within a group unit-major (the units are sorted by
+// decreasing cost, so the heavy units of the group start first), group after
+// group, so its L2 holds the U of kYGroup blocks (1.2 MB at 2J = 8) whatever
+// the system size.  Also writes the unit's share of the energy,
+// (1/3) sum_q Re(Y~ conj(U~)) over its rows, to Epart.
 constexpr int kYGroup = 4;
 template <int TJ>
 __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_compute_y(
@@ -147,8 +181,7 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
     const double *__restrict__ beta, int per_atom_beta, int nb,
     const double *__restrict__ gscale, double *__restrict__ Epart)
 {
-    __shared__ double2 yw[kYWaves][kYMaxQ][64];
-    __shared__ double cqs[kYWaves][kCqMax];
+    __shared__ double2 yw[kYWaves][y_unit_rows(TJ)][TJ / 2 + 1][64];
     const int unit = blockIdx.x;
     const int nrows = (int)gridDim.x / nblk8;
     const int nbx = nblk8 >> 3;  // blocks per XCD
@@ -170,11 +203,13 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
     const int J = __builtin_amdgcn_readfirstlane(row->J);
     const int p = __builtin_amdgcn_readfirstlane(row->p);
     const int nq = __builtin_amdgcn_readfirstlane(row->nq);
+    const int two = __builtin_amdgcn_readfirstlane(row->two);
     const double gs = gscale ? gscale[asafe] : 1.0;
 
-    double2 y[TJ / 2 + 1];
+    // the wave's sums of the unit's rows, in LDS
+    double2 *ysum = &yw[w][0][0][0];
 #pragma unroll
-    for (int q = 0; q <= TJ / 2; ++q) y[q] = make_double2(0.0, 0.0);
+    for (int k = 0; k < y_unit_rows(TJ) * (TJ / 2 + 1); ++k) ysum[k * 64 + lane] = make_double2(0.0, 0.0);
     const int cb = __builtin_amdgcn_readfirstlane(row->cb[w]);
     const int ce = __builtin_amdgcn_readfirstlane(row->cb[w + 1]);
     for (int c = cb; c < ce; ++c) {
@@ -187,46 +222,31 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
         const int cp_off = __builtin_amdgcn_readfirstlane(C->cp_off);
         const int cq_off = __builtin_amdgcn_readfirstlane(C->cq_off);
         const int cl = __builtin_amdgcn_readfirstlane(C->l);
-        // stage this contribution's cq table in the wavefront's LDS slice,
-        // rows padded with zeros to 2J_max + 1 entries
-        for (int k = lane; k < nq * (TJ + 1); k += 64) {
-            const int q = k / (TJ + 1), q1 = k - q * (TJ + 1);
-            cqs[w][k] = (q1 <= J1) ? cqt[cq_off + q * (J1 + 1) + q1] : 0.0;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // the contribution's weight (multiplicity, beta, per-atom scale)
-        // rides on the row coefficient, so products accumulate into y
+        // rides on the row coefficients, so products accumulate into y
         const double bl = per_atom_beta ? beta[(size_t)asafe * nb + cl] : beta[cl];
         const double f = C->factor * bl * gs;
-        YDispatch<TJ, 0>::run(D, J1, J2, p1lo, p1hi, cp_off, p, nq, U, npad, voff, cpt, cqs[w], f,
-                              y);
-        // the next contribution overwrites the staged table
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        YDispatch<TJ, 0>::run(D, J1, J2, p1lo, p1hi, cp_off, p, nq, two, U, npad, voff, cpt,
+                              cqt + cq_off, f, ysum, lane);
     }
-#pragma unroll
-    for (int q = 0; q <= TJ / 2; ++q)
-        if (q < nq) yw[w][q][lane] = y[q];
     __syncthreads();
     if (w == 0) {
         double e = 0.0;
-        for (int q = 0; q < nq; ++q) {
-            double2 s = yw[0][q][lane];
+        for (int r = 0; r < y_unit_rows(TJ) && r <= two; ++r)
+            for (int q = 0; q < nq; ++q) {
+                double2 s = yw[0][r][q][lane];
 #pragma unroll
-            for (int v = 1; v < kYWaves; ++v) {
-                s.x += yw[v][q][lane].x;
-                s.y += yw[v][q][lane].y;
+                for (int v = 1; v < kYWaves; ++v) {
+                    s.x += yw[v][r][q][lane].x;
+                    s.y += yw[v][r][q][lane].y;
+                }
+                const double sc = row->oscale[r][q];
+                s.x *= sc;
+                s.y *= sc;
+                Y[(size_t)(row->ebase + r + q * (J + 1)) * npad + atom] = s;
+                const double2 u = U[(size_t)(row->frow + r * (J + 1) + q) * npad + atom];
+                e += (s.x * u.x + s.y * u.y) * row->einv[r][q];
             }
-            const double sc = row->oscale[q];
-            s.x *= sc;
-            s.y *= sc;
-            Y[(size_t)(row->ebase + q * (J + 1)) * npad + atom] = s;
-            const double2 u = U[(size_t)(row->frow + q) * npad + atom];
-            e += (s.x * u.x + s.y * u.y) * row->einv[q];
-        }
         if (Epart && atom < n) Epart[(size_t)rix * npad + atom] = e;
     }
 }
