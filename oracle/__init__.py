@@ -59,6 +59,11 @@ def _load():
             ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
             ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int,
             ip, ip, ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.oracle_snap_elements.restype = ctypes.c_int
+        lib.oracle_snap_elements.argtypes = [
+            ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+            ctypes.c_double, ctypes.c_int, ip, dp, dp, ctypes.c_double, dp, ctypes.c_int,
+            ip, ip, ctypes.c_int, dp, dp, dp, dp, dp]
         lib.oracle_max_threads.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         _lib = lib
@@ -176,6 +181,47 @@ def snap(pos, box, twojmax, rcut, rfac0=0.99363, rmin0=0.0, switch_flag=1, wself
         out["U"] = U[..., 0] + 1j * U[..., 1]
     if want_dE:
         out["dE"] = dE[:st].copy()
+    return out
+
+
+def snap_elements(pos, box, twojmax, types, radius, weight, rcutfac, beta, rfac0=0.99363,
+                  rmin0=0.0, switch_flag=1, wself=1.0, nthreads=0, want_utot=False):
+    """Several elements: atom i has element types[i]; element e has radius
+    radius[e] and density weight weight[e]; the pair (i, k) has the cutoff
+    rcutfac (radius[t_i] + radius[t_k]) and enters U_i with weight[t_k];
+    ``beta`` is [n_elements, N_B], the coefficients of the centre's element.
+    The neighbour list (``off``/``nbr``) is searched to rcutfac * 2 max(radius)
+    and keeps the pairs beyond their own cutoff (their ``dE`` rows are zero).
+    Returns the same dict as :func:`snap`."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    radius = np.ascontiguousarray(radius, dtype=np.float64)
+    weight = np.ascontiguousarray(weight, dtype=np.float64)
+    n = pos.shape[0]
+    nb = lib.oracle_components(twojmax, None)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    assert beta.shape == (len(radius), nb) and weight.shape == radius.shape and types.shape == (n,)
+    _, nbr_nb = neighbors(pos, box, 2.0 * rcutfac * float(radius.max()))
+    cap = max(1, len(nbr_nb))
+    off = np.zeros(n + 1, dtype=np.int32)
+    nbr = np.zeros(cap, dtype=np.int32)
+    E = np.zeros(n)
+    F = np.zeros((n, 3))
+    B = np.zeros((n, max(nb, 1)))
+    _, ufull = ufull_offsets(twojmax)
+    U = np.zeros((n, ufull, 2)) if want_utot else None
+    dE = np.zeros((cap, 3))
+    st = lib.oracle_snap_elements(n, _dp(pos), _dp(box), twojmax, rfac0, rmin0, int(switch_flag),
+                                  wself, len(radius), _ip(types), _dp(radius), _dp(weight),
+                                  float(rcutfac), _dp(beta), int(nthreads), _ip(off), _ip(nbr),
+                                  cap, _dp(E), _dp(F), _dp(B), _dp(U), _dp(dE))
+    if st < 0:
+        raise RuntimeError("oracle_snap_elements failed with status %d" % st)
+    out = dict(E=E, F=F, B=B[:, :nb], off=off, nbr=nbr[:st].copy(), dE=dE[:st].copy())
+    if want_utot:
+        out["U"] = U[..., 0] + 1j * U[..., 1]
     return out
 
 

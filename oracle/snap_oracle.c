@@ -41,7 +41,13 @@
  *     J1+J2+J even, ordered J1 ascending, then J2 ascending, then J
  *     ascending;
  *   - the pair derivative dE_p = dE_i/dr_ik for p = (i -> k); the force on
- *     i gains +dE_p and the force on k gains -dE_p.
+ *     i gains +dE_p and the force on k gains -dE_p;
+ *   - several elements (the density weights Sec. II.A leaves out): element
+ *     e has a radius R_e and a weight w_e; the pair (i, k) has the cutoff
+ *     R_ik = rcutfac (R_t(i) + R_t(k)), used in the 3-sphere map and f_c of
+ *     that pair, and enters U_i with the weight of the neighbour's element,
+ *     w_t(k) f_c u; pairs with r_ik >= R_ik contribute nothing; E_i uses
+ *     the coefficients of the centre's element.
  *
  * Parallelism: OpenMP over central atoms, one private force array per
  * thread, reduced in thread order.
@@ -326,10 +332,32 @@ static int ublock(int J)
  *  Returns the number of pairs, -1 on bad arguments, -2 if pair_cap is too
  *  small, -3 on coincident atoms.
  */
-int oracle_snap(int n, const double *pos, const double box[3], int twojmax, double rcut,
-                double rfac0, double rmin0, int switch_flag, double wself, const double *beta,
-                int per_atom_beta, int ncenter, const int *centers, int nthreads, int *off,
-                int *nbr, int pair_cap, double *E, double *F, double *B, double *Utot, double *dE)
+/* element description (NULL: one element, the cutoff rcut, unit weights) */
+typedef struct {
+    int nelem;
+    const int *type;       /* [n], 0 .. nelem-1 */
+    const double *radius;  /* [nelem] */
+    const double *weight;  /* [nelem] */
+    double rcutfac;
+} oelem;
+
+/* cutoff and density weight of the pair (i, k) */
+static void pair_cut(const oelem *el, double rcut, int i, int k, double *rc, double *w)
+{
+    if (!el) {
+        *rc = rcut;
+        *w = 1.0;
+        return;
+    }
+    *rc = el->rcutfac * (el->radius[el->type[i]] + el->radius[el->type[k]]);
+    *w = el->weight[el->type[k]];
+}
+
+static int snap_eval(int n, const double *pos, const double box[3], int twojmax, double rcut,
+                     double rfac0, double rmin0, int switch_flag, double wself, const oelem *el,
+                     const double *beta, int per_atom_beta, int ncenter, const int *centers,
+                     int nthreads, int *off, int *nbr, int pair_cap, double *E, double *F,
+                     double *B, double *Utot, double *dE)
 {
     if (n < 0 || twojmax < 0 || twojmax > ORACLE_MAXJ || rcut <= 0.0) return -1;
     const int np = oracle_neighbors(n, pos, box, rcut, off, nbr, pair_cap);
@@ -388,7 +416,8 @@ int oracle_snap(int n, const double *pos, const double box[3], int twojmax, doub
         for (int ci = 0; ci < ncent; ++ci) {
             const int i = centers ? centers[ci] : ci;
             if (i < 0 || i >= n) continue;
-            const double *bet = per_atom_beta ? beta + (size_t)i * nb : beta;
+            const double *bet = el ? beta + (size_t)el->type[i] * nb
+                                   : per_atom_beta ? beta + (size_t)i * nb : beta;
 
             /* eq. (u): Utot_i = w_self I + sum_k f_c u(r_ik) */
             for (int J = 0; J <= twojmax; ++J) {
@@ -402,12 +431,17 @@ int oracle_snap(int n, const double *pos, const double box[3], int twojmax, doub
                 min_image(pos + 3 * i, pos + 3 * nbr[t], box, rv);
                 const double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
                 if (r < 1e-10) { bad = 1; continue; }
+                double rc, w;
+                pair_cut(el, rcut, i, nbr[t], &rc, &w);
+                if (r >= rc) continue;
+                oparams Pp = P;
+                Pp.rcut = rc;
                 ogeom g;
-                geometry(rv, &P, &g);
+                geometry(rv, &Pp, &g);
                 for (int J = 0; J <= twojmax; ++J) {
                     wigner(J, g.a, g.b, u + ublock(J), NULL, NULL, NULL);
                     cplx *UJ = U + ublock(J);
-                    for (int e = 0; e < (J + 1) * (J + 1); ++e) UJ[e] += g.fc * u[ublock(J) + e];
+                    for (int e = 0; e < (J + 1) * (J + 1); ++e) UJ[e] += w * g.fc * u[ublock(J) + e];
                 }
             }
             if (bad) {
@@ -471,9 +505,13 @@ int oracle_snap(int n, const double *pos, const double box[3], int twojmax, doub
                     min_image(pos + 3 * i, pos + 3 * k, box, rv);
                     const double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
                     double de[3] = {0.0, 0.0, 0.0};
-                    if (r >= 1e-10) {
+                    double rc, w;
+                    pair_cut(el, rcut, i, k, &rc, &w);
+                    if (r >= 1e-10 && r < rc) {
+                        oparams Pp = P;
+                        Pp.rcut = rc;
                         ogeom g;
-                        geometry(rv, &P, &g);
+                        geometry(rv, &Pp, &g);
                         for (int J = 0; J <= twojmax; ++J) {
                             const int o = ublock(J), sz = (J + 1) * (J + 1);
                             cplx dtmp[3 * (ORACLE_MAXJ + 1) * (ORACLE_MAXJ + 1)];
@@ -481,7 +519,8 @@ int oracle_snap(int n, const double *pos, const double box[3], int twojmax, doub
                             /* d(f_c u)/dr_alpha = grad f_c u + f_c du/dr_alpha */
                             for (int al = 0; al < 3; ++al)
                                 for (int e = 0; e < sz; ++e)
-                                    du[al * ufull + o + e] = g.dfc[al] * u[o + e] + g.fc * dtmp[al * sz + e];
+                                    du[al * ufull + o + e] =
+                                        w * (g.dfc[al] * u[o + e] + g.fc * dtmp[al * sz + e]);
                         }
                         for (int l = 0; l < nb; ++l) {
                             const int J1 = tri[3 * l], J2 = tri[3 * l + 1], J = tri[3 * l + 2];
@@ -520,6 +559,43 @@ int oracle_snap(int n, const double *pos, const double box[3], int twojmax, doub
     free(tri);
 #undef CGT
     return status;
+}
+
+int oracle_snap(int n, const double *pos, const double box[3], int twojmax, double rcut,
+                double rfac0, double rmin0, int switch_flag, double wself, const double *beta,
+                int per_atom_beta, int ncenter, const int *centers, int nthreads, int *off,
+                int *nbr, int pair_cap, double *E, double *F, double *B, double *Utot, double *dE)
+{
+    return snap_eval(n, pos, box, twojmax, rcut, rfac0, rmin0, switch_flag, wself, NULL, beta,
+                     per_atom_beta, ncenter, centers, nthreads, off, nbr, pair_cap, E, F, B, Utot,
+                     dE);
+}
+
+/*
+ * oracle_snap_elements: as oracle_snap for several elements (see the header
+ * of this file): type[n] in 0..nelem-1, radius[nelem], weight[nelem],
+ * rcutfac; beta[nelem][N_B], the coefficients of each centre element.
+ * Neighbours are searched to rcutfac * 2 max(radius); pairs beyond their own
+ * cutoff stay in the list with zero contribution.  Returns as oracle_snap,
+ * -1 also for a type out of range.
+ */
+int oracle_snap_elements(int n, const double *pos, const double box[3], int twojmax, double rfac0,
+                         double rmin0, int switch_flag, double wself, int nelem, const int *type,
+                         const double *radius, const double *weight, double rcutfac,
+                         const double *beta, int nthreads, int *off, int *nbr, int pair_cap,
+                         double *E, double *F, double *B, double *Utot, double *dE)
+{
+    if (nelem < 1 || !type || !radius || !weight || !(rcutfac > 0.0)) return -1;
+    double rmax = 0.0;
+    for (int e = 0; e < nelem; ++e) {
+        if (!(radius[e] > 0.0)) return -1;
+        if (radius[e] > rmax) rmax = radius[e];
+    }
+    for (int i = 0; i < n; ++i)
+        if (type[i] < 0 || type[i] >= nelem) return -1;
+    const oelem el = {nelem, type, radius, weight, rcutfac};
+    return snap_eval(n, pos, box, twojmax, 2.0 * rcutfac * rmax, rfac0, rmin0, switch_flag, wself,
+                     &el, beta, 0, 0, NULL, nthreads, off, nbr, pair_cap, E, F, B, Utot, dE);
 }
 
 int oracle_max_threads(void)
