@@ -139,6 +139,31 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
                  int per_atom_beta, double *energy, double *force, double *bispec,
                  double *dE_pair, void *stream);
 
+/* Several elements (the density weights and per-element radii that
+ * Sec. II.A leaves out of eq. (u), deferring to the SNAP reference it
+ * cites).  Element e has radius[e] > 0 and density weight weight[e]; the pair
+ * (i, k) has the cutoff R_ik = rcutfac (radius[t_i] + radius[t_k]), used in
+ * its 3-sphere map and switching function, and enters U_i as
+ * weight[t_k] f_c(r_ik) u_j(r_ik); pairs with r_ik >= R_ik contribute
+ * nothing.  The largest cutoff 2 rcutfac max(radius) must not exceed the
+ * context's rcut, which stays the neighbour-list cutoff.  Host arrays of
+ * nelem (1..64) entries, copied; nelem = 0 removes the elements.
+ * Errors: SNAP_EINVAL. */
+int snap_set_elements(snap_ctx *c, int nelem, const double *radius, const double *weight,
+                      double rcutfac);
+
+/* snap_compute for several elements (after snap_set_elements):
+ *   type  dev int[n], the element of each atom (0..nelem-1; a type out of
+ *         range is reported by the next snap_sync_status as SNAP_EINVAL)
+ *   beta  dev double[nelem][N_B], the coefficients of each element: E_i uses
+ *         those of atom i's element (eq. snapatomenergy per element)
+ * Other arguments, outputs and errors as snap_compute; the neighbour list is
+ * built to the context's rcut. */
+int snap_compute_elements(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                          const int *off, const int *nbr, const int *rev, const int *type,
+                          const double *beta, double *energy, double *force, double *bispec,
+                          double *dE_pair, void *stream);
+
 /* The forward half used by automatic differentiation: compute_U and the
  * bispectrum only.  energy = sum_l beta_l B_l per atom; energy may be NULL
  * (then beta is not read and may be NULL too).  Other arguments as in

@@ -16,8 +16,18 @@
 
 using namespace snapmi;
 
+// elements a context may describe (snap_set_elements)
+constexpr int kMaxElements = 64;
+
 struct snap_ctx {
     snap_params prm;
+    // several elements: radius, density weight per element, pair cutoff
+    // factor; device copies uploaded on the next call after a change
+    int nelem = 0;
+    std::vector<double> erad, ewt;
+    double rcutfac = 0.0;
+    bool elem_dirty = false;
+    double *d_erad = nullptr, *d_ewt = nullptr;
     Tables tab;
     DevTables dev;
     bool dev_ready = false;
@@ -126,6 +136,10 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(w.pair_atom);
     (void)hipFree(w.flag);
     w = Work();
+    (void)hipFree(c->d_erad);
+    (void)hipFree(c->d_ewt);
+    c->d_erad = c->d_ewt = nullptr;
+    c->elem_dirty = c->nelem > 0;
     c->dev_ready = false;
     c->cap_atoms = c->cap_pairs = 0;
 }
@@ -419,19 +433,42 @@ static int run_u(snap_ctx *c, int n, int npairs, const double *pos, const Geom &
     return SNAP_OK;
 }
 
-int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
-                 const int *off, const int *nbr, const int *rev, const double *beta,
-                 int per_atom_beta, double *energy, double *force, double *bispec,
-                 double *dE_pair, void *stream)
+// Upload the element arrays after snap_set_elements changed them.
+static int ensure_elements(snap_ctx *c)
+{
+    if (!c->elem_dirty) return SNAP_OK;
+    (void)hipFree(c->d_erad);
+    (void)hipFree(c->d_ewt);
+    c->d_erad = c->d_ewt = nullptr;
+    HIP_TRY(upload(c->d_erad, c->erad), "upload element radii");
+    HIP_TRY(upload(c->d_ewt, c->ewt), "upload element weights");
+    c->elem_dirty = false;
+    return SNAP_OK;
+}
+
+// snap_compute and snap_compute_elements (type != NULL: beta per element)
+static int compute_impl(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                        const int *off, const int *nbr, const int *rev, const int *type,
+                        const double *beta, int per_atom_beta, double *energy, double *force,
+                        double *bispec, double *dE_pair, void *stream)
 {
     int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
     if (st) return st;
     if (n > 0 && (!energy || !force)) return fail(SNAP_EINVAL, "NULL output pointer");
+    if (type && c->nelem < 1) return fail(SNAP_EINVAL, "no elements set (snap_set_elements)");
     if ((st = ensure_device(c))) return st;
+    if (type && (st = ensure_elements(c))) return st;
     if (n == 0) return SNAP_OK;
     hipStream_t s = (hipStream_t)stream;
     if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
-    const Geom g = make_geom(c, box);
+    Geom g = make_geom(c, box);
+    if (type) {
+        g.type = type;
+        g.erad = c->d_erad;
+        g.ewt = c->d_ewt;
+        g.rcutfac = c->rcutfac;
+        g.nelem = c->nelem;
+    }
     Work &w = c->work;
     const int nb = c->tab.nb;
     double *dE = dE_pair ? dE_pair : w.dE;
@@ -443,7 +480,7 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
     {
         StageTimer tm(c, 1, s);
         HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, beta, per_atom_beta,
-                                 nb, nullptr, w.Epart, s),
+                                 nb, type, c->nelem, nullptr, w.Epart, s),
                 "compute_Y launch");
         tm.finish();
     }
@@ -469,6 +506,58 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
     }
     c->last_n = n;
     return SNAP_OK;
+}
+
+int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                 const int *off, const int *nbr, const int *rev, const double *beta,
+                 int per_atom_beta, double *energy, double *force, double *bispec,
+                 double *dE_pair, void *stream)
+{
+    return compute_impl(c, n, npairs, pos, box, off, nbr, rev, nullptr, beta, per_atom_beta,
+                        energy, force, bispec, dE_pair, stream);
+}
+
+int snap_set_elements(snap_ctx *c, int nelem, const double *radius, const double *weight,
+                      double rcutfac)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    if (nelem < 0 || nelem > kMaxElements)
+        return fail(SNAP_EINVAL, "nelem %d outside 0..%d", nelem, kMaxElements);
+    if (nelem == 0) {
+        c->nelem = 0;
+        c->erad.clear();
+        c->ewt.clear();
+        return SNAP_OK;
+    }
+    if (!radius || !weight) return fail(SNAP_EINVAL, "NULL element array");
+    if (!(rcutfac > 0.0) || !std::isfinite(rcutfac)) return fail(SNAP_EINVAL, "rcutfac must be > 0");
+    double rmax = 0.0;
+    for (int e = 0; e < nelem; ++e) {
+        if (!(radius[e] > 0.0) || !std::isfinite(radius[e]))
+            return fail(SNAP_EINVAL, "radius[%d] must be > 0", e);
+        if (!std::isfinite(weight[e])) return fail(SNAP_EINVAL, "weight[%d] must be finite", e);
+        rmax = radius[e] > rmax ? radius[e] : rmax;
+    }
+    if (2.0 * rcutfac * rmax > c->prm.rcut * (1.0 + 1e-12))
+        return fail(SNAP_EINVAL,
+                    "largest pair cutoff %g exceeds the context's rcut %g (the neighbour "
+                    "list cutoff)", 2.0 * rcutfac * rmax, c->prm.rcut);
+    c->nelem = nelem;
+    c->erad.assign(radius, radius + nelem);
+    c->ewt.assign(weight, weight + nelem);
+    c->rcutfac = rcutfac;
+    c->elem_dirty = true;
+    return SNAP_OK;
+}
+
+int snap_compute_elements(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                          const int *off, const int *nbr, const int *rev, const int *type,
+                          const double *beta, double *energy, double *force, double *bispec,
+                          double *dE_pair, void *stream)
+{
+    if (n > 0 && !type) return fail(SNAP_EINVAL, "NULL type pointer");
+    return compute_impl(c, n, npairs, pos, box, off, nbr, rev, n > 0 ? type : nullptr, beta, 0,
+                        energy, force, bispec, dE_pair, stream);
 }
 
 int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
@@ -508,7 +597,7 @@ int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const doubl
     Work &w = c->work;
     double *dE = dE_pair ? dE_pair : w.dE;
     HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, beta, per_atom_beta,
-                             c->tab.nb, grad_energy, nullptr, s),
+                             c->tab.nb, nullptr, 0, grad_energy, nullptr, s),
             "compute_Y launch");
     if (npairs > 0)
         HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom, w.Y,
@@ -570,6 +659,7 @@ int snap_sync_status(snap_ctx *c, void *stream)
     HIP_TRY(hipMemcpy(&flag, c->work.flag, sizeof(int), hipMemcpyDeviceToHost), "read flag");
     if (flag) {
         HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
+        if (flag == 2) return fail(SNAP_EINVAL, "atom type outside 0..nelem-1");
         return fail(SNAP_EGEOM, "coincident atoms (r < 1e-10 A) or non-finite positions");
     }
     return SNAP_OK;
@@ -626,8 +716,8 @@ int snap_jacobian(snap_ctx *c, int n, int npairs, const double *pos, const doubl
     if (npairs == 0) return SNAP_OK;
     for (int l = 0; l < nb; ++l) {
         const double *el = c->dev.onehot + (size_t)l * nb;
-        HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, el, 0, nb, nullptr,
-                                 nullptr, s),
+        HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, el, 0, nb, nullptr, 0,
+                                 nullptr, nullptr, s),
                 "compute_Y launch");
         HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
                             w.Y, c->dev, g, w.dE, s),

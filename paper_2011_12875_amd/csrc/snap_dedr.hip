@@ -228,9 +228,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     // Y~ of J = 0 and of the first level of column 0, ahead of the geometry
     const double y00 = load_row(Y, 0, npad, (unsigned)i * 16u).x;
     double rv[3];
-    min_image(pos, i, nbr[tt], g, rv);
+    const int k = nbr[tt];
+    min_image(pos, i, k, g, rv);
+    double rc, wk;
+    pair_cut(g, i, k, rc, wk);
     PairGeom pg;
-    const bool ok = pair_geometry(rv, g, pg);
+    const bool ok = pair_geometry(rv, g, rc, wk, pg);
 
     // d a / d r_alpha, d b / d r_alpha and d f_c / d r_alpha
     double2 da[ND], db[ND];

@@ -57,12 +57,34 @@ struct PairGeom {
     double r, c0, s0, dth0;
 };
 
-// The 3-sphere map of eq. (u): theta0 = rfac0 pi (r - rmin0)/(rcut - rmin0),
-// Cayley-Klein pair a = cos theta0 - i sin theta0 n_z,
-// b = sin theta0 (n_y - i n_x), switching function f_c and df_c/dr.
-// Returns false for r < 1e-10 or non-finite input (the pair then contributes
-// nothing: f_c = 0, a = 1, b = 0).
-__device__ __forceinline__ bool pair_geometry(const double rv[3], const Geom &g, PairGeom &pg)
+// Cutoff rc and density weight w of the pair (i, k): rcut and 1 for one
+// element; for several, rcutfac (R_t(i) + R_t(k)) and the weight of the
+// neighbour's element (the density weights eq. (u) leaves out).  A type
+// outside 0..nelem-1 is clamped (no read out of range) and returns false.
+__device__ __forceinline__ bool pair_cut(const Geom &g, int i, int k, double &rc, double &w)
+{
+    if (!g.type) {
+        rc = g.rcut;
+        w = 1.0;
+        return true;
+    }
+    int ti = g.type[i], tk = g.type[k];
+    const bool ok = ti >= 0 && ti < g.nelem && tk >= 0 && tk < g.nelem;
+    ti = ti < 0 ? 0 : (ti >= g.nelem ? g.nelem - 1 : ti);
+    tk = tk < 0 ? 0 : (tk >= g.nelem ? g.nelem - 1 : tk);
+    rc = g.rcutfac * (g.erad[ti] + g.erad[tk]);
+    w = g.ewt[tk];
+    return ok;
+}
+
+// The 3-sphere map of eq. (u) with the pair cutoff rc:
+// theta0 = rfac0 pi (r - rmin0)/(rc - rmin0), Cayley-Klein pair
+// a = cos theta0 - i sin theta0 n_z, b = sin theta0 (n_y - i n_x), and the
+// switching function times the pair's density weight, w f_c and w df_c/dr
+// (zero from rc on).  Returns false for r < 1e-10 or non-finite input (the
+// pair then contributes nothing: f_c = 0, a = 1, b = 0).
+__device__ __forceinline__ bool pair_geometry(const double rv[3], const Geom &g, double rc,
+                                              double w, PairGeom &pg)
 {
     const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     const double r = sqrt(r2);
@@ -72,7 +94,7 @@ __device__ __forceinline__ bool pair_geometry(const double rv[3], const Geom &g,
     pg.n[0] = ok ? rv[0] / rs : 0.0;
     pg.n[1] = ok ? rv[1] / rs : 0.0;
     pg.n[2] = ok ? rv[2] / rs : 1.0;
-    const double span = g.rcut - g.rmin0;
+    const double span = rc - g.rmin0;
     const double th0 = g.rfac0 * M_PI * (rs - g.rmin0) / span;
     double s0, c0;
     sincos(th0, &s0, &c0);
@@ -88,9 +110,9 @@ __device__ __forceinline__ bool pair_geometry(const double rv[3], const Geom &g,
         fc = 0.5 * (cx + 1.0);
         dfdr = -0.5 * M_PI / span * sx;
     }
-    const bool inside = ok && r < g.rcut;
-    pg.fc = inside ? fc : 0.0;
-    pg.dfdr = inside ? dfdr : 0.0;
+    const bool inside = ok && r < rc;
+    pg.fc = inside ? w * fc : 0.0;
+    pg.dfdr = inside ? w * dfdr : 0.0;
     return ok;
 }
 

@@ -11,6 +11,13 @@ struct Geom {
     double rcut, rfac0, rmin0, wself;
     double box[3];
     int switch_flag;
+    // several elements (type == nullptr: one element, cutoff rcut, unit
+    // weights): the pair (i, k) has the cutoff rcutfac (erad[t_i] + erad[t_k])
+    // and density weight ewt[t_k]; device arrays
+    const int *type = nullptr;
+    const double *erad = nullptr, *ewt = nullptr;
+    double rcutfac = 0.0;
+    int nelem = 0;
 };
 
 // Device copies of the tables of one context.
@@ -45,9 +52,12 @@ hipError_t launch_compute_u(int twojmax, int n, int npad, const double *pos, con
                             const int *nbr, const DevTables &T, const Geom &g, double2 *U,
                             int *pair_atom, int *flag, hipStream_t s);
 
+// coefficients: beta[nb] shared, beta[n][nb] per atom (per_atom_beta), or
+// beta[nelem][nb] per element of btype[n] (btype not NULL)
 hipError_t launch_compute_y(int twojmax, int n, int npad, const double2 *U, double2 *Y,
                             const DevTables &T, const double *beta, int per_atom_beta, int nb,
-                            const double *gscale, double *Epart, hipStream_t s);
+                            const int *btype, int nelem, const double *gscale, double *Epart,
+                            hipStream_t s);
 
 // B (and, when energy is not NULL, energy = beta . B); nfull = number of full
 // U elements (small 2J stage U in LDS)

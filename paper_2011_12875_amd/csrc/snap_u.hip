@@ -252,8 +252,12 @@ __device__ __forceinline__ void slot_geometry(bool valid, int i, int t, bool fir
     if (valid) {
         if (first) pair_atom[t] = i;
         double rv[3];
-        min_image(pos, i, nbr[t], g, rv);
-        if (!pair_geometry(rv, g, pg) && first) flag[0] = 1;
+        const int k = nbr[t];
+        min_image(pos, i, k, g, rv);
+        double rc, w;
+        const bool typed = pair_cut(g, i, k, rc, w);
+        if (!pair_geometry(rv, g, rc, w, pg) && first) flag[0] = 1;
+        if (!typed && first) flag[0] = 2;
     }
 }
 

@@ -178,8 +178,8 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
     int n, int npad, int nblk8, const double2 *__restrict__ U, double2 *__restrict__ Y,
     const YRowC *__restrict__ rows, const YContrib *__restrict__ contribs,
     const double *__restrict__ cpt, const double *__restrict__ cqt,
-    const double *__restrict__ beta, int per_atom_beta, int nb,
-    const double *__restrict__ gscale, double *__restrict__ Epart)
+    const double *__restrict__ beta, int per_atom_beta, int nb, const int *__restrict__ btype,
+    int nelem, const double *__restrict__ gscale, double *__restrict__ Epart)
 {
     __shared__ double2 yw[kYWaves][y_unit_rows(TJ)][TJ / 2 + 1][64];
     const int unit = blockIdx.x;
@@ -205,6 +205,14 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
     const int nq = __builtin_amdgcn_readfirstlane(row->nq);
     const int two = __builtin_amdgcn_readfirstlane(row->two);
     const double gs = gscale ? gscale[asafe] : 1.0;
+    // coefficient row of this atom: its own (per-atom), its element's
+    // (several elements; the type is clamped, a bad one is reported by
+    // compute_U), or the one shared row
+    int brow = per_atom_beta ? asafe : 0;
+    if (btype) {
+        const int t = btype[asafe];
+        brow = t < 0 ? 0 : (t >= nelem ? nelem - 1 : t);
+    }
 
     // the wave's sums of the unit's rows, in LDS
     double2 *ysum = &yw[w][0][0][0];
@@ -224,7 +232,7 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
         const int cl = __builtin_amdgcn_readfirstlane(C->l);
         // the contribution's weight (multiplicity, beta, per-atom scale)
         // rides on the row coefficients, so products accumulate into y
-        const double bl = per_atom_beta ? beta[(size_t)asafe * nb + cl] : beta[cl];
+        const double bl = beta[(size_t)brow * nb + cl];
         const double f = C->factor * bl * gs;
         YDispatch<TJ, 0>::run(D, J1, J2, p1lo, p1hi, cp_off, p, nq, two, U, npad, voff, cpt,
                               cqt + cq_off, f, ysum, lane);
@@ -260,23 +268,26 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
 
 template <int TJ>
 hipError_t launch_y_t(int n, int npad, const double2 *U, double2 *Y, const DevTables &T,
-                      const double *beta, int per_atom_beta, int nb, const double *gscale,
-                      double *Epart, hipStream_t s)
+                      const double *beta, int per_atom_beta, int nb, const int *btype, int nelem,
+                      const double *gscale, double *Epart, hipStream_t s)
 {
     const int nblk8 = (((n + 63) / 64) + 7) / 8 * 8;
     hipLaunchKernelGGL(k_compute_y<TJ>, dim3(T.nyrows * nblk8), dim3(64 * kYWaves), 0, s, n, npad,
                        nblk8, U, Y, T.yrows, T.ycontrib, T.ycp, T.ycq, beta,
-                       per_atom_beta, nb, gscale, Epart);
+                       per_atom_beta, nb, btype, nelem, gscale, Epart);
     return hipGetLastError();
 }
 
 hipError_t launch_compute_y(int twojmax, int n, int npad, const double2 *U, double2 *Y,
                             const DevTables &T, const double *beta, int per_atom_beta, int nb,
-                            const double *gscale, double *Epart, hipStream_t s)
+                            const int *btype, int nelem, const double *gscale, double *Epart,
+                            hipStream_t s)
 {
     switch (twojmax) {
 #define X(k) \
-    case k: return launch_y_t<k>(n, npad, U, Y, T, beta, per_atom_beta, nb, gscale, Epart, s);
+    case k:  \
+        return launch_y_t<k>(n, npad, U, Y, T, beta, per_atom_beta, nb, btype, nelem, gscale, \
+                             Epart, s);
         SNAP_TJ_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -27,7 +27,7 @@ EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_n
            "snap_stage_times", "snap_sync_status", "snap_last_error",
            "snap_mlp_nparams", "snap_mlp_workspace", "snap_mlp_forward", "snap_mlp_grad",
            "snap_adam_step", "snap_jacobian", "snap_jacobian_forces", "snap_jacobian_adjoint",
-           "snap_fit_residuals", "snap_virial"]
+           "snap_fit_residuals", "snap_virial", "snap_set_elements", "snap_compute_elements"]
 
 
 class SnapError(RuntimeError):
@@ -65,6 +65,8 @@ def load():
         "snap_build_neighbors": (i, [dp, i, dp, d, ip, ip, ip, i, ip]),
         "snap_check_neighbors": (i, [i, ip, ip, ip, i]),
         "snap_compute": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp, vp]),
+        "snap_set_elements": (i, [vp, i, dp, dp, d]),
+        "snap_compute_elements": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "snap_forward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp]),
         "snap_backward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp]),
         "snap_copy_workspace": (i, [vp, i, vp, vp]),
@@ -254,6 +256,46 @@ class SnapPotential:
             self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
             self._stream()))
         self._fwd_token += 1  # U of this call replaces that of the last forward
+        return out
+
+    def set_elements(self, radius, weight, rcutfac):
+        """Several elements: radius and density weight per element and the
+        pair cutoff factor (pair cutoff rcutfac (R_t_i + R_t_k) <= rcut)."""
+        radius = np.ascontiguousarray(radius, dtype=np.float64)
+        weight = np.ascontiguousarray(weight, dtype=np.float64)
+        assert radius.ndim == 1 and weight.shape == radius.shape
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().snap_set_elements(self._ctx, len(radius), radius.ctypes.data_as(dp),
+                                        weight.ctypes.data_as(dp), float(rcutfac)))
+        self.nelem = len(radius)
+
+    def compute_elements(self, pos, box, nl, types, beta, bispectrum=False, pair_derivs=False,
+                         out=None):
+        """compute() for several elements: types [n] int32 on the device,
+        beta [nelem, N_B] float64 on the device (coefficients per element)."""
+        import torch
+        assert pos.dtype == torch.float64 and pos.is_cuda and pos.is_contiguous()
+        n = pos.shape[0]
+        assert nl.n == n
+        assert types.dtype == torch.int32 and types.is_cuda and types.shape == (n,)
+        assert types.is_contiguous()
+        assert beta.dtype == torch.float64 and beta.is_cuda and beta.is_contiguous()
+        assert beta.shape == (getattr(self, "nelem", 0), self.ncoeff)
+        boxa = (ctypes.c_double * 3)(*[float(x) for x in box])
+        dev = pos.device
+        if out is None:
+            out = {"energy": torch.empty(n, dtype=torch.float64, device=dev),
+                   "force": torch.empty((n, 3), dtype=torch.float64, device=dev)}
+            if bispectrum:
+                out["bispectrum"] = torch.empty((n, self.ncoeff), dtype=torch.float64, device=dev)
+            if pair_derivs:
+                out["dE"] = torch.empty((max(nl.npairs, 1), 3), dtype=torch.float64, device=dev)
+        _check(load().snap_compute_elements(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(types), self._ptr(beta), self._ptr(out["energy"]),
+            self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
+            self._stream()))
+        self._fwd_token += 1
         return out
 
     def forward(self, pos, box, nl, beta, bispectrum=None):

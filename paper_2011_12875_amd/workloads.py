@@ -95,6 +95,34 @@ WORKLOADS = {
 }
 
 
+# Several elements (synthetic; the paper's benchmark has one element): the
+# positions of a one-element workload, each atom given an element at random
+# (fraction frac of element 1), per-element radius and density weight, pair
+# cutoff rcutfac (R_t_i + R_t_k) (the largest, 2 * 2.365, is RCUT), and
+# coefficients per element.
+ELEMENT_WORKLOADS = {
+    "bcc2000_2j8_2el": dict(base="bcc2000_2j8", radius=(2.365, 2.05), weight=(1.0, 0.62),
+                            rcutfac=1.0, frac=0.5, type_seed=14, beta_seed=15),
+    "bcc128_2j4_3el": dict(base="bcc128_2j4", radius=(2.365, 2.05, 2.2), weight=(1.0, 0.62, 1.3),
+                           rcutfac=1.0, frac=None, type_seed=16, beta_seed=17),
+}
+
+
+def make_elements(name: str):
+    """(pos, box, types int32 [n], radius, weight, rcutfac, beta [nelem, N_B],
+    twojmax) for a named several-element workload."""
+    w = ELEMENT_WORKLOADS[name]
+    pos, box, _, tj = make(w["base"])
+    nelem = len(w["radius"])
+    rng = np.random.default_rng(w["type_seed"])
+    if w["frac"] is not None and nelem == 2:
+        types = (rng.random(len(pos)) < w["frac"]).astype(np.int32)
+    else:
+        types = rng.integers(0, nelem, len(pos)).astype(np.int32)
+    b = np.stack([beta(ncoeff(tj), w["beta_seed"] + e) for e in range(nelem)])
+    return (pos, box, types, np.array(w["radius"]), np.array(w["weight"]), w["rcutfac"], b, tj)
+
+
 def make(name: str):
     """Return (pos, box, beta, twojmax) for a named workload."""
     w = WORKLOADS[name]

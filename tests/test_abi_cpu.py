@@ -48,6 +48,28 @@ def test_setup_validates_parameters():
     assert lib.snap_ncoeff(None) == -1
 
 
+def test_set_elements_validates():
+    lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.snap_setup(4, 4.73, 0.99363, 0.0, 1, ctypes.byref(ctx)) == 0
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def call(rad, wt, f):
+        r = np.ascontiguousarray(rad, dtype=np.float64)
+        w = np.ascontiguousarray(wt, dtype=np.float64)
+        return lib.snap_set_elements(ctx, len(r), r.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                     float(f))
+    assert call([2.0, 2.3], [1.0, 0.5], 1.0) == 0
+    assert call([2.4], [1.0], 0.98) == 0                 # 4.704 <= 4.73
+    assert call([2.4], [1.0], 1.0) == -1                 # 4.8 > rcut
+    assert call([2.0, 0.0], [1.0, 1.0], 1.0) == -1       # radius must be > 0
+    assert call([2.0], [float("nan")], 1.0) == -1
+    assert call([2.0], [1.0], 0.0) == -1
+    assert call(np.full(65, 1.0), np.ones(65), 1.0) == -1
+    assert lib.snap_set_elements(ctx, 0, None, None, 0.0) == 0   # back to one element
+    assert lib.snap_destroy(ctx) == 0
+
+
 @pytest.mark.parametrize("tj,nb,nh", [(0, 1, 1), (2, 5, 9), (4, 14, 32), (8, 55, 155),
                                       (14, 204, 652)])
 def test_table_sizes(tj, nb, nh):
