@@ -437,6 +437,8 @@ static int run_u(snap_ctx *c, int n, int npairs, const double *pos, const Geom &
 static int ensure_elements(snap_ctx *c)
 {
     if (!c->elem_dirty) return SNAP_OK;
+    // earlier calls may still read the old arrays
+    if (c->d_erad || c->d_ewt) HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     (void)hipFree(c->d_erad);
     (void)hipFree(c->d_ewt);
     c->d_erad = c->d_ewt = nullptr;

@@ -148,8 +148,9 @@ __device__ __forceinline__ void u_emit(UStage &st, int lane, const UPair2<TJ> &w
     }
 }
 
-// Levels J..TJ of column Q, each emitted to the staging buffer.
-template <int TJ, int Q, int J>
+// Levels J..TJ of column Q, each emitted to the staging buffer; with SEED,
+// level 2Q+1 is also mirrored into the seed of column Q+1.
+template <int TJ, int Q, int J, bool SEED>
 struct ULevels {
     __device__ __forceinline__ static void run(UStage &st, int lane, UPair2<TJ> &w, int i0, int n,
                                                int npad, int chunk, double wself,
@@ -157,12 +158,21 @@ struct ULevels {
     {
         step2<TJ>(J, w);
         u_emit<TJ, Q, J>(st, lane, w, i0, n, npad, chunk, wself, U);
+        if constexpr (SEED && J == 2 * Q + 1) {
+            mirror_seed<TJ, Q>(w.c0, w.s0);
+            mirror_seed<TJ, Q>(w.c1, w.s1);
+#pragma unroll
+            for (int p = 0; p <= 2 * Q + 1; ++p) {
+                pin(w.s0[p]);
+                pin(w.s1[p]);
+            }
+        }
         memory_fence_compiler();
-        ULevels<TJ, Q, J + 1>::run(st, lane, w, i0, n, npad, chunk, wself, U);
+        ULevels<TJ, Q, J + 1, SEED>::run(st, lane, w, i0, n, npad, chunk, wself, U);
     }
 };
-template <int TJ, int Q>
-struct ULevels<TJ, Q, TJ + 1> {
+template <int TJ, int Q, bool SEED>
+struct ULevels<TJ, Q, TJ + 1, SEED> {
     __device__ __forceinline__ static void run(UStage &, int, UPair2<TJ> &, int, int, int, int,
                                                double, double2 *__restrict__)
     {
@@ -208,8 +218,23 @@ struct USeedPath {
     }
 };
 
-// Column Q of one chunk of pairs: seed path, column walk, final flush.
-template <int TJ, int Q>
+// Columns Q..TJ/2 walked one after another, each from the seed the previous
+// walk left (CHAIN), or column Q alone (its seed path first when Q > 0).
+template <int TJ, int Q, bool CHAIN>
+__device__ __forceinline__ void u_walk(UStage &st, int lane, UPair2<TJ> &w, double fc0, double fc1,
+                                       int i0, int n, int npad, int chunk, double wself,
+                                       double2 *__restrict__ U)
+{
+    constexpr bool NEXT = CHAIN && Q < TJ / 2;
+    start_column<TJ, Q>(w, fc0, fc1);
+    if constexpr (Q == 0) u_emit<TJ, 0, 0>(st, lane, w, i0, n, npad, chunk, wself, U);
+    ULevels<TJ, Q, (Q == 0 ? 1 : 2 * Q), NEXT>::run(st, lane, w, i0, n, npad, chunk, wself, U);
+    u_flush<stage_end(TJ, Q)>(st, lane, i0, n, npad, chunk, wself, U);
+    if constexpr (NEXT) u_walk<TJ, Q + 1, true>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
+}
+
+// Workgroup column Q of one chunk of pairs: the seed path, then the walk.
+template <int TJ, int Q, bool CHAIN>
 __device__ __forceinline__ void u_column(UStage &st, int lane, UPair2<TJ> &w, double fc0,
                                          double fc1, int i0, int n, int npad, int chunk,
                                          double wself, double2 *__restrict__ U)
@@ -217,22 +242,30 @@ __device__ __forceinline__ void u_column(UStage &st, int lane, UPair2<TJ> &w, do
 #pragma unroll
     for (int p = 0; p <= TJ; ++p) w.s0[p] = w.s1[p] = make_double2(0.0, 0.0);
     USeedPath<TJ, 0, Q>::run(w, fc0, fc1);
-    start_column<TJ, Q>(w, fc0, fc1);
-    if constexpr (Q == 0) u_emit<TJ, 0, 0>(st, lane, w, i0, n, npad, chunk, wself, U);
-    ULevels<TJ, Q, (Q == 0 ? 1 : 2 * Q)>::run(st, lane, w, i0, n, npad, chunk, wself, U);
-    u_flush<stage_end(TJ, Q)>(st, lane, i0, n, npad, chunk, wself, U);
+    u_walk<TJ, Q, CHAIN>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
 }
 
-// uniform column index -> compile-time instance
+// Workgroups per group of atoms.  Up to 2J = 4 one walks every column in
+// turn: the pair geometry (square root, two sine-cosine pairs, divisions)
+// then costs more than the short columns, and the split would compute it
+// once per column.  Above, one workgroup per column: with its seed path each
+// costs about the same ((2J_max+1)(2J_max+2)/2 elements, 45 at 2J = 8).
+template <int TJ>
+constexpr int kUGroups = (TJ <= 4) ? 1 : TJ / 2 + 1;
+
+// uniform workgroup column index -> compile-time instance
 template <int TJ, int Q>
 struct UColumn {
     __device__ __forceinline__ static void run(int col, UStage &st, int lane, UPair2<TJ> &w,
                                                double fc0, double fc1, int i0, int n, int npad,
                                                int chunk, double wself, double2 *__restrict__ U)
     {
-        if constexpr (Q <= TJ / 2) {
+        if constexpr (kUGroups<TJ> == 1) {
+            (void)col;
+            u_column<TJ, 0, true>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
+        } else if constexpr (Q <= TJ / 2) {
             if (col == Q)
-                u_column<TJ, Q>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
+                u_column<TJ, Q, false>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
             else
                 UColumn<TJ, Q + 1>::run(col, st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
         }
@@ -268,7 +301,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     int *__restrict__ pair_atom, int *__restrict__ flag)
 {
     __shared__ UStage st;
-    constexpr int NCOL = TJ / 2 + 1;
+    constexpr int NCOL = kUGroups<TJ>;
     const int lane = threadIdx.x;
     const int colq = (int)blockIdx.x % NCOL;  // uniform
     if (lane == 0) st.table = uinfo;  // read after the first flush's barrier
@@ -306,7 +339,7 @@ hipError_t launch_u_t(int n, int npad, const double *pos, const int *off, const 
                       const Geom &g, const UInfo *uinfo, double2 *U, int *pair_atom, int *flag,
                       hipStream_t s)
 {
-    const int nblk = ((n + kUAtoms - 1) / kUAtoms) * (TJ / 2 + 1);
+    const int nblk = ((n + kUAtoms - 1) / kUAtoms) * kUGroups<TJ>;
     hipLaunchKernelGGL(k_compute_u<TJ>, dim3(nblk), dim3(64), 0, s, n, npad, pos, off, nbr, g,
                        uinfo, U, pair_atom, flag);
     return hipGetLastError();
