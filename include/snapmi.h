@@ -66,7 +66,8 @@ typedef struct {
     double rmin0;      /* [0, rcut)                                           */
     int switch_flag;   /* 0 or 1                                              */
     double wself;      /* self weight on the diagonal of every U_j (1.0)     */
-    int dedr_dirs;     /* directions per lane in compute_dE: 1 or 3 (0: auto) */
+    int dedr_dirs;     /* directions per lane in compute_dE: 1 or 3 (0: auto,
+                        * 3 up to 2J = 6, 1 above)                            */
 } snap_params;
 
 /* Create a context for one parameter set.  Builds the host index tables
