@@ -125,6 +125,33 @@ def cpu_baseline(pos, box, beta, twojmax, budget_s=12.0):
                       "the oracle's O(N^2) neighbour search)" % (reps, n, dt)}
 
 
+def surrogate_step_timing(steps, warmup):
+    """The surrogate's inference step alone (2J = 4 descriptors, network, 2J = 4
+    adjoint stages), no gate read-back, on the 16 000-atom configuration; the
+    network is seeded but untrained: the kernels and their cost do not depend
+    on the weights."""
+    import torch
+    from paper_2011_12875_amd import snapmi, surrogate as sg, workloads as wl
+    pot4, pot8 = snapmi.SnapPotential(4, wl.RCUT), snapmi.SnapPotential(8, wl.RCUT)
+    pos, box = wl.surrogate_inference_config()
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    tpos = torch.as_tensor(pos, device="cuda")
+    _, B = pot4.forward(tpos, box, nl, None)
+    Bn = B.cpu().numpy()
+    net = sg.Network.initial(14, Bn.mean(0), Bn.std(0), 0.0, 1.0, seed=1)
+    sp = sg.SurrogatePotential(net, pot4, pot8, wl.surrogate_target_beta())
+    for _ in range(warmup):
+        sp.compute(tpos, box, nl, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sp.compute(tpos, box, nl, check=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"surrogate_step_ms": ms, "atoms": len(pos), "pairs": nl.npairs, "steps": steps,
+            "note": "untrained seeded network, range gate off"}
+
+
 def surrogate_leg(epochs, steps, warmup, log=None):
     """Train the surrogate on the 10^4 seeded 250-atom configurations (labels
     from 2J = 8 SNAP, descriptors and Jacobians from 2J = 4), judge it against
@@ -213,6 +240,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=100)
+    ap.add_argument("--surrogate-step", action="store_true",
+                    help="only time the surrogate's inference step on the 16 000-atom "
+                         "configuration with a seeded, untrained network and the range gate "
+                         "off (a kernel-trace target), print one JSON line and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device 3 times (a kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -227,6 +258,10 @@ def main():
 
     from paper_2011_12875_amd import snapmi
     from paper_2011_12875_amd import workloads as wl
+
+    if args.surrogate_step:
+        print(json.dumps(surrogate_step_timing(args.steps, args.warmup)), flush=True)
+        return
 
     elements = args.workload in wl.ELEMENT_WORKLOADS
     if elements:
