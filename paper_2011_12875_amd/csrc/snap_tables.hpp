@@ -56,7 +56,7 @@ struct BItem {
 //   p2 = p - p1 + d, q2 = q - q1 + d, d = (J1 + J2 - J)/2,
 // with true (unscaled) U values; cp and cq are Clebsch-Gordan coefficients.
 // A unit of compute_Y holds the rows p and p + 1 of one J (p alone for the
-// last row of an even J, and every row when 2J_max > 9): row p + 1 pairs U^J1 row p1 with the U^J2 row
+// last row of an even J): row p + 1 pairs U^J1 row p1 with the U^J2 row
 // that row p pairs with p1 - 1, so each loaded row serves both.  The p1
 // range of a contribution is the union of the two rows' ranges, and cp
 // holds two values per p1 (zero where that row has no valid p2).
@@ -70,9 +70,10 @@ struct YContrib {
     int32_t pad;
 };
 
-// Rows per unit: two while the second row's registers fit (2J_max <= 9),
-// one above.
-constexpr int y_unit_rows(int twojmax) { return twojmax <= 9 ? 2 : 1; }
+// Rows per unit: two for every supported 2J_max (the contribution's sums are
+// added to LDS, so the second row costs registers only for its own sums and
+// the U^J2 row it keeps); the single-row form stays for larger 2J_max.
+constexpr int y_unit_rows(int twojmax) { return twojmax <= 14 ? 2 : 1; }
 
 // A unit (rows p, p + 1 of J) of Y, split over the waves of one workgroup:
 // contributions of wave w are cb[w] .. cb[w+1]-1.
