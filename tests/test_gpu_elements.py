@@ -94,3 +94,31 @@ def test_bad_type_reported():
     pot.compute_elements(dev["pos"], box, nl, dev["types"], dev["beta"])
     pot.sync_status()
     torch.cuda.synchronize()
+
+
+def test_elements_isolated_and_open_box():
+    """Open box, two elements: a dimer inside its pair cutoff, a dimer of the
+    same distance beyond it (smaller radii), and an isolated atom."""
+    import torch
+    from paper_2011_12875_amd import snapmi
+    pos = np.array([[0.0, 0.0, 0.0], [2.9, 0.3, -0.2],        # A-A at ~2.92 < 2*1.6
+                    [20.0, 0.0, 0.0], [22.9, 0.3, -0.2],      # B-B at ~2.92 > 2*1.4
+                    [40.0, 5.0, 5.0]])
+    types = np.array([0, 0, 1, 1, 0], dtype=np.int32)
+    box = np.zeros(3)
+    rad, wt, f, tj = np.array([1.6, 1.4]), np.array([1.0, 0.8]), 1.0, 6
+    beta = np.stack([wl.beta(wl.ncoeff(tj), 50), wl.beta(wl.ncoeff(tj), 51)])
+    pot = snapmi.SnapPotential(tj, wl.RCUT)
+    pot.set_elements(rad, wt, f)
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    out = pot.compute_elements(torch.as_tensor(pos, device="cuda"), box, nl,
+                               torch.as_tensor(types, device="cuda"),
+                               torch.as_tensor(beta, device="cuda"), bispectrum=True)
+    pot.sync_status()
+    o = oracle.snap_elements(pos, box, tj, types, rad, wt, f, beta)
+    E = out["energy"].cpu().numpy()
+    scale = np.maximum(np.abs(o["E"]), np.abs(o["E"]).mean())
+    assert (np.abs(E - o["E"]) / scale).max() <= E_REL
+    assert np.abs(out["force"].cpu().numpy() - o["F"]).max() <= F_ABS
+    F = out["force"].cpu().numpy()
+    assert np.abs(F[0]).max() > 0.0 and np.all(F[2:] == 0.0)
