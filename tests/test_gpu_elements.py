@@ -59,6 +59,11 @@ def test_elements_parity(name):
     # both elements' pair cutoffs are exercised: some listed pairs are beyond
     # their own cutoff (zero derivative) and some inside
     assert (np.abs(dE).sum(1) == 0.0).any() and (np.abs(dE).sum(1) > 0.0).any()
+    # the virial from these pair derivatives (pairs beyond their cutoff add 0)
+    W = pot.virial(dev["pos"], box, nl, out["dE"])
+    Wref, _ = oracle.virial(pos, box, o["off"], o["nbr"], o["dE"])
+    W = W.cpu().numpy().reshape(3, 3)
+    assert np.abs(W - Wref).max() <= 1e-10 * np.abs(Wref).max()
 
 
 def test_one_element_equals_snap_compute():
