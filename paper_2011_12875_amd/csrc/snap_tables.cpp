@@ -285,7 +285,9 @@ int build_neighbors(const double *pos, int n, const double box[3], double rcut, 
             }
             lo[d] = mn;
             ext[d] = mx - mn;
-            nc[d] = std::max(1, (int)std::floor(ext[d] / rcut) + 1);
+            // cells at least rcut wide, as on a periodic axis, so that the
+            // +-1 neighbouring cells hold every partner within rcut
+            nc[d] = std::max(1, (int)std::floor(ext[d] / rcut));
         }
         nc[d] = std::min(nc[d], 1024);
     }

@@ -19,22 +19,28 @@ RFAC0 = 0.99363
 RMIN0 = 0.0
 
 
-def bcc(ncell: int, sigma: float, seed: int, a: float = A_BCC):
-    """BCC crystal of ncell^3 cubic cells with Gaussian displacements.
+def bcc(ncell, sigma: float, seed: int, a: float = A_BCC, open_axes=()):
+    """BCC crystal of ncell^3 cubic cells (or nx x ny x nz for a tuple: an
+    orthorhombic box) with Gaussian displacements.
 
-    Atom order is cell-major: index = ((ix*n + iy)*n + iz)*2 + basis.
-    Returns (pos [N,3] float64 wrapped into [0, L), box [3]).
+    Atom order is cell-major: index = ((ix*ny + iy)*nz + iz)*2 + basis.
+    Returns (pos [N,3] float64 wrapped into [0, L), box [3]); the axes in
+    open_axes are not periodic (box entry 0, positions not wrapped).
     """
+    nx, ny, nz = (ncell, ncell, ncell) if np.isscalar(ncell) else tuple(ncell)
     rng = np.random.default_rng(seed)
-    idx = np.arange(ncell)
-    ix, iy, iz = np.meshgrid(idx, idx, idx, indexing="ij")
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
     corner = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
     basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]])
     sites = (corner[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
-    L = ncell * a
+    L = np.array([nx, ny, nz], dtype=np.float64) * a
     pos = sites + rng.normal(0.0, sigma, size=sites.shape)
-    pos = np.mod(pos, L)
-    return np.ascontiguousarray(pos), np.array([L, L, L])
+    for d in range(3):
+        if d in open_axes:
+            L[d] = 0.0
+        else:
+            pos[:, d] = np.mod(pos[:, d], L[d])
+    return np.ascontiguousarray(pos), L
 
 
 def bcc_with_vacancies(ncell: int, nvac: int, sigma: float, vac_seed: int, pos_seed: int,

@@ -166,3 +166,41 @@ def test_neighbor_errors():
         with pytest.raises(snapmi.SnapError) as e:
             snapmi.check_neighbors(o, n_, r)
         assert e.value.code == -3
+
+
+def _same_lists(pos, box, rcut):
+    off, nbr, rev = snapmi.build_neighbors(pos, box, rcut)
+    ooff, onbr = oracle.neighbors(pos, box, rcut)
+    assert np.array_equal(off, ooff)
+    for i in range(len(pos)):
+        assert set(nbr[off[i]:off[i + 1]]) == set(onbr[ooff[i]:ooff[i + 1]]), i
+    snapmi.check_neighbors(off, nbr, rev)
+    return off
+
+
+def test_neighbor_builder_open_axis_wider_than_two_cutoffs():
+    """On an open axis whose extent exceeds 2 rcut the cells must still be at
+    least rcut wide: a pair in cells two apart would otherwise be lost."""
+    pos = np.array([[0.0, 0.0, 0.0], [0.8, 0.0, 0.0], [1.7, 0.0, 0.0], [2.5, 0.0, 0.0]])
+    off = _same_lists(pos, np.zeros(3), 1.0)
+    assert off[-1] == 6   # (0,1), (1,2), (2,3) in both directions
+    for seed in (0, 1, 2):
+        cpos, cbox = wl.cluster(300, 9.0, seed)
+        _same_lists(cpos, cbox, wl.RCUT)
+
+
+@pytest.mark.parametrize("open_axes", [(2,), (0, 1)])
+def test_neighbor_builder_partly_open_box(open_axes):
+    """Slab and wire geometries: some axes periodic, the others open and
+    several cut-offs long."""
+    pos, box = wl.bcc((5, 4, 6), 0.1, 21, open_axes=open_axes)
+    assert all(box[d] == 0.0 for d in open_axes)
+    off = _same_lists(pos, box, wl.RCUT)
+    counts = np.diff(off)
+    assert counts.min() < 26 and counts.max() >= 24
+
+
+def test_neighbor_builder_orthorhombic_box():
+    pos, box = wl.bcc((4, 5, 7), 0.1, 22)
+    assert len(set(box.tolist())) == 3
+    _same_lists(pos, box, wl.RCUT)
