@@ -134,7 +134,11 @@ int snap_check_neighbors(int n, const int *off, const int *nbr, const int *rev, 
  *   stream  hipStream_t (NULL = default stream)
  * Work is enqueued on the stream and the call returns without waiting.
  * Coincident atoms are detected on the device and reported by the next
- * snap_sync_status.  Errors: SNAP_EINVAL, SNAP_EBOX, SNAP_ENOMEM, SNAP_EDEV. */
+ * snap_sync_status.  Sizes: n <= 2^24, npairs <= 2^30, and
+ * 16 (twojmax + 1) npad < 2^31 with npad = n rounded up to 64 (a row of U_J
+ * is addressed with 32-bit byte counts: at most 8 947 840 atoms at 2J = 14,
+ * 14 913 024 at 2J = 8).  Errors: SNAP_EINVAL (also for sizes beyond these
+ * limits), SNAP_EBOX, SNAP_ENOMEM, SNAP_EDEV. */
 int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
                  const int *off, const int *nbr, const int *rev, const double *beta,
                  int per_atom_beta, double *energy, double *force, double *bispec,
@@ -176,8 +180,12 @@ int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double
 /* The reverse sweep (Sec. IV: the adjoint Y is reverse-mode differentiation
  * of B with respect to U): given g_i = dL/dE_i (dev double[n]), computes
  * force = -dL/dr (dev double[n][3]) with Y built from the per-atom
- * coefficients g_i * beta, using the U_j kept by the last snap_forward on the
- * same context and stream.  dE_pair as in snap_compute (may be NULL). */
+ * coefficients g_i * beta, using the U_j and pair->atom map kept by the last
+ * snap_forward (or snap_compute, snap_jacobian) on the same context and
+ * stream.  That call must have had the same n and npairs, and no call that
+ * grew the context's workspace may have come in between; otherwise
+ * SNAP_EINVAL and nothing is enqueued.  dE_pair as in snap_compute (may be
+ * NULL). */
 int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
                   const int *off, const int *nbr, const int *rev, const double *beta,
                   int per_atom_beta, const double *grad_energy, double *force, double *dE_pair,
@@ -198,8 +206,24 @@ int snap_virial(snap_ctx *c, int n, int npairs, const double *pos, const double 
 
 /* Copy an internal per-atom array of the last call into dst (dev memory):
  * which = 0: U_j, which = 1: Y_j.  Layout: double[nhalf][n][2] (element-
- * major, re/im interleaved), elements in the order of snap_table(1). */
-int snap_copy_workspace(snap_ctx *c, int which, double *dst, void *stream);
+ * major, re/im interleaved), elements in the order of snap_table(1).  n must
+ * be the atom count of the last forward-type call (it sizes dst); otherwise
+ * SNAP_EINVAL. */
+int snap_copy_workspace(snap_ctx *c, int which, int n, double *dst, void *stream);
+
+/* Derivative of the weighted energy L = sum_i g_i E_i, E_i = beta . B_i
+ * (eq. (snapatomenergy)), with respect to the coefficients: the backward
+ * pass of automatic differentiation for beta (Sec. IV treats the adjoint as
+ * reverse-mode differentiation; this is its coefficient part).
+ *   grad_energy dev double[n]      g_i
+ *   bispec      dev double[n][N_B] B_i (from snap_forward or snap_compute)
+ *   per_atom = 0: grad_beta dev double[N_B] = sum_i g_i B_i, summed per block
+ *                 of 256 atoms and then over the blocks, always in the same
+ *                 order (deterministic);
+ *   per_atom = 1: grad_beta dev double[n][N_B] = g_i B_i.
+ * Errors: SNAP_EINVAL, SNAP_ENOMEM, SNAP_EDEV. */
+int snap_beta_grad(snap_ctx *c, int n, const double *grad_energy, const double *bispec,
+                   int per_atom, double *grad_beta, void *stream);
 
 /* Stage timing with HIP events recorded on the call's stream, around each
  * stage of every later snap_compute / snap_forward / snap_backward while

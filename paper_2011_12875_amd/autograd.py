@@ -7,8 +7,10 @@ differentiation of B with respect to U: with upstream g_i = dL/dE_i it builds
 Y from the per-atom coefficients g_i * beta (compute_Y), runs the fused
 derivative kernel (compute_dE) and gathers forces, so
     dL/dr     = -F(g),
-    dL/dbeta  = sum_i g_i B_i   (or g_i B_i for per-atom coefficients).
-Double backward is not supported.
+    dL/dbeta  = sum_i g_i B_i   (or g_i B_i for per-atom coefficients),
+the latter by the library's fixed-order reduction (snap_beta_grad).  Double
+backward is not supported: the backward is once-differentiable, so asking for
+a second derivative raises instead of returning a gradient without a graph.
 """
 from __future__ import annotations
 
@@ -29,6 +31,7 @@ class _SnapEnergy(torch.autograd.Function):
         return E
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, gE):
         pos, beta, B = ctx.saved_tensors
         pot = ctx.pot
@@ -41,10 +44,7 @@ class _SnapEnergy(torch.autograd.Function):
             F = pot.backward(pos, ctx.box, ctx.nl, beta, gE)
             grad_pos = -F
         if ctx.needs_input_grad[1]:
-            if beta.dim() == 1:
-                grad_beta = gE @ B
-            else:
-                grad_beta = gE[:, None] * B
+            grad_beta = pot.beta_grad(gE, B, per_atom=beta.dim() == 2)
         return grad_pos, grad_beta, None, None, None
 
 

@@ -35,7 +35,18 @@ struct snap_ctx {
     Work work;
     int cap_atoms = 0;   // npad the per-atom workspace holds
     int cap_pairs = 0;   // pairs the dE / pair_atom workspace holds
+    // The U_j and pair->atom map of the last forward-type call (snap_compute,
+    // snap_forward, snap_jacobian) serve snap_backward and
+    // snap_copy_workspace: their sizes, and the workspace generation they
+    // were written in (every reallocation of U or pair_atom starts a new
+    // generation, whose contents no call has written yet).
     int last_n = 0;
+    int last_npairs = 0;
+    unsigned long long gen = 0, last_gen = ~0ull;
+    // per-block partial sums of snap_virial and snap_beta_grad (their own
+    // buffer: growing it never touches U)
+    double *part = nullptr;
+    size_t cap_part = 0;
     // stage timing (snap_profile): event pairs recorded per stage
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -131,7 +142,6 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(w.U);
     (void)hipFree(w.Y);
     (void)hipFree(w.Epart);
-    (void)hipFree(w.vpart);
     (void)hipFree(w.dE);
     (void)hipFree(w.pair_atom);
     (void)hipFree(w.flag);
@@ -139,6 +149,9 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(c->d_erad);
     (void)hipFree(c->d_ewt);
     c->d_erad = c->d_ewt = nullptr;
+    (void)hipFree(c->part);
+    c->part = nullptr;
+    c->cap_part = 0;
     c->elem_dirty = c->nelem > 0;
     c->dev_ready = false;
     c->cap_atoms = c->cap_pairs = 0;
@@ -193,17 +206,15 @@ static int ensure_work(snap_ctx *c, int n, int np, hipStream_t s)
         (void)hipFree(w.U);
         (void)hipFree(w.Y);
         (void)hipFree(w.Epart);
-        (void)hipFree(w.vpart);
         w.U = w.Y = nullptr;
-        w.Epart = w.vpart = nullptr;
+        w.Epart = nullptr;
         c->cap_atoms = 0;
+        ++c->gen;
         HIP_TRY(hipMalloc((void **)&w.U, sizeof(double2) * (size_t)c->tab.nfullel * npad),
                 "alloc U");
         HIP_TRY(hipMalloc((void **)&w.Y, sizeof(double2) * nh * npad), "alloc Y");
         HIP_TRY(hipMalloc((void **)&w.Epart, sizeof(double) * c->tab.yrows.size() * npad),
                 "alloc Epart");
-        HIP_TRY(hipMalloc((void **)&w.vpart, sizeof(double) * 9 * (size_t)(npad / 256 + 1)),
-                "alloc virial partials");
         HIP_TRY(hipMemset(w.U, 0, sizeof(double2) * (size_t)c->tab.nfullel * npad), "clear U");
         HIP_TRY(hipMemset(w.Y, 0, sizeof(double2) * nh * npad), "clear Y");
         c->cap_atoms = npad;
@@ -215,6 +226,7 @@ static int ensure_work(snap_ctx *c, int n, int np, hipStream_t s)
         w.dE = nullptr;
         w.pair_atom = nullptr;
         c->cap_pairs = 0;
+        ++c->gen;
         HIP_TRY(hipMalloc((void **)&w.dE, sizeof(double) * 3 * (size_t)np), "alloc dE");
         HIP_TRY(hipMalloc((void **)&w.pair_atom, sizeof(int) * (size_t)np), "alloc pair_atom");
         c->cap_pairs = np;
@@ -222,6 +234,28 @@ static int ensure_work(snap_ctx *c, int n, int np, hipStream_t s)
     // element-major arrays use the capacity as their stride
     w.npad = c->cap_atoms;
     return SNAP_OK;
+}
+
+// Grow the partial-sum buffer to at least `doubles` entries (waits for the
+// stream first: earlier calls may still read it).
+static int ensure_part(snap_ctx *c, size_t doubles, hipStream_t s)
+{
+    if (doubles <= c->cap_part) return SNAP_OK;
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    (void)hipFree(c->part);
+    c->part = nullptr;
+    c->cap_part = 0;
+    HIP_TRY(hipMalloc((void **)&c->part, sizeof(double) * doubles), "alloc partial sums");
+    c->cap_part = doubles;
+    return SNAP_OK;
+}
+
+// A forward-type call wrote U_j and the pair->atom map for (n, npairs).
+static void record_forward(snap_ctx *c, int n, int npairs)
+{
+    c->last_n = n;
+    c->last_npairs = npairs;
+    c->last_gen = c->gen;
 }
 
 static int check_params(const snap_params *p)
@@ -418,6 +452,12 @@ static int common_checks(snap_ctx *c, int n, int npairs, const double *pos, cons
     if (!c) return fail(SNAP_EINVAL, "NULL context");
     if (n < 0 || npairs < 0) return fail(SNAP_EINVAL, "negative size");
     if (n > (1 << 24) || npairs > (1 << 30)) return fail(SNAP_EINVAL, "size too large");
+    // compute_Y addresses a row of U_J (J + 1 elements of npad atoms, 16 bytes
+    // each) through one buffer descriptor with 32-bit byte counts
+    const long long npad = ((long long)n + 63) / 64 * 64;
+    if ((long long)(c->prm.twojmax + 1) * npad * 16 >= (1ll << 31))
+        return fail(SNAP_EINVAL, "n = %d too large for twojmax %d (limit %lld atoms)", n,
+                    c->prm.twojmax, (long long)(((1ll << 31) - 1) / (16 * (c->prm.twojmax + 1))) / 64 * 64);
     int st = check_box(box, c->prm.rcut);
     if (st) return st;
     if (n > 0 && (!pos || !off || (need_beta && !beta)))
@@ -510,7 +550,7 @@ static int compute_impl(snap_ctx *c, int n, int npairs, const double *pos, const
                 "bispectrum launch");
         tm.finish();
     }
-    c->last_n = n;
+    record_forward(c, n, npairs);
     return SNAP_OK;
 }
 
@@ -582,7 +622,7 @@ int snap_forward(snap_ctx *c, int n, int npairs, const double *pos, const double
     HIP_TRY(launch_bispectrum(n, c->work.npad, c->work.U, c->dev, c->tab.nb, bispec, beta,
                               per_atom_beta, energy, s, c->tab.nfullel),
             "bispectrum launch");
-    c->last_n = n;
+    record_forward(c, n, npairs);
     return SNAP_OK;
 }
 
@@ -594,11 +634,14 @@ int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const doubl
     int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
     if (st) return st;
     if (n > 0 && (!grad_energy || !force)) return fail(SNAP_EINVAL, "NULL gradient pointer");
-    if (n != c->last_n) return fail(SNAP_EINVAL, "snap_backward needs a snap_forward with the same n");
-    if ((st = ensure_device(c))) return st;
     if (n == 0) return SNAP_OK;
+    // the U_j and pair->atom map of the last forward-type call are reused:
+    // same sizes, and no reallocation of the workspace since
+    if (!c->dev_ready || n != c->last_n || npairs != c->last_npairs || c->gen != c->last_gen)
+        return fail(SNAP_EINVAL,
+                    "snap_backward needs the U of a snap_forward (or snap_compute) on this "
+                    "context with the same n and npairs, and no larger call in between");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
     const Geom g = make_geom(c, box);
     Work &w = c->work;
     double *dE = dE_pair ? dE_pair : w.dE;
@@ -614,10 +657,13 @@ int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const doubl
     return SNAP_OK;
 }
 
-int snap_copy_workspace(snap_ctx *c, int which, double *dst, void *stream)
+int snap_copy_workspace(snap_ctx *c, int which, int n, double *dst, void *stream)
 {
     if (!c || !dst || (which != 0 && which != 1)) return fail(SNAP_EINVAL, "bad arguments");
-    if (!c->dev_ready || c->last_n <= 0) return fail(SNAP_EINVAL, "no evaluation to copy from");
+    if (!c->dev_ready || c->last_n <= 0 || c->gen != c->last_gen)
+        return fail(SNAP_EINVAL, "no evaluation to copy from");
+    if (n != c->last_n)
+        return fail(SNAP_EINVAL, "n = %d but the last evaluation had %d atoms", n, c->last_n);
     // the workspace holds scaled values (U/N and w N Y); return true ones
     const double2 *src = which == 0 ? c->work.U : c->work.Y;
     const int *map = which == 0 ? c->dev.half2full : nullptr;
@@ -683,15 +729,29 @@ int snap_virial(snap_ctx *c, int n, int npairs, const double *pos, const double 
     if (npairs > 0 && !dE_pair) return fail(SNAP_EINVAL, "NULL dE_pair pointer");
     if ((st = ensure_device(c))) return st;
     hipStream_t s = (hipStream_t)stream;
-    if ((st = ensure_work(c, n > 0 ? n : 1, npairs > 0 ? npairs : 1, s))) return st;
+    if ((st = ensure_part(c, 9 * ((size_t)n / 256 + 1), s))) return st;
     const Geom g = make_geom(c, box);
-    if (n == 0) {
-        HIP_TRY(launch_virial(0, pos, off, nbr, g, dE_pair, nullptr, c->work.vpart, virial, s),
-                "virial launch");
-        return SNAP_OK;
-    }
-    HIP_TRY(launch_virial(n, pos, off, nbr, g, dE_pair, virial_atom, c->work.vpart, virial, s),
+    HIP_TRY(launch_virial(n, pos, off, nbr, g, dE_pair, n > 0 ? virial_atom : nullptr, c->part,
+                          virial, s),
             "virial launch");
+    return SNAP_OK;
+}
+
+int snap_beta_grad(snap_ctx *c, int n, const double *grad_energy, const double *bispec,
+                   int per_atom, double *grad_beta, void *stream)
+{
+    if (!c) return fail(SNAP_EINVAL, "NULL context");
+    if (n < 0 || n > (1 << 24)) return fail(SNAP_EINVAL, "n out of range");
+    if (per_atom != 0 && per_atom != 1) return fail(SNAP_EINVAL, "per_atom must be 0 or 1");
+    if (!grad_beta || (n > 0 && (!grad_energy || !bispec)))
+        return fail(SNAP_EINVAL, "NULL pointer argument");
+    int st = ensure_device(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!per_atom && (st = ensure_part(c, (size_t)beta_grad_blocks(n) * c->tab.nb + 1, s)))
+        return st;
+    HIP_TRY(launch_beta_grad(n, c->tab.nb, grad_energy, bispec, per_atom, c->part, grad_beta, s),
+            "coefficient gradient launch");
     return SNAP_OK;
 }
 
@@ -718,7 +778,7 @@ int snap_jacobian(snap_ctx *c, int n, int npairs, const double *pos, const doubl
         HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, bispec, nullptr, 0, nullptr, s,
                                   c->tab.nfullel),
                 "bispectrum launch");
-    c->last_n = n;
+    record_forward(c, n, npairs);
     if (npairs == 0) return SNAP_OK;
     for (int l = 0; l < nb; ++l) {
         const double *el = c->dev.onehot + (size_t)l * nb;

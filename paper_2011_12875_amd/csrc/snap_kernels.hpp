@@ -42,7 +42,6 @@ struct Work {
     double2 *U = nullptr, *Y = nullptr;
     double *dE = nullptr;
     double *Epart = nullptr;  // [nyrows][npad] per-row shares of the energy
-    double *vpart = nullptr;  // [npad/256 + 1][9] per-block virial sums
     int *pair_atom = nullptr;
     int *flag = nullptr;
     int npad = 0;
@@ -89,6 +88,12 @@ hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *
 hipError_t launch_virial(int n, const double *pos, const int *off, const int *nbr, const Geom &g,
                          const double *dE, double *watom, double *partial, double *out,
                          hipStream_t s);
+
+// dE/dbeta of sum_i g_i E_i: out[nb] = sum_i g_i B[i][:] in a fixed order
+// (part: beta_grad_blocks(n) * nb doubles), or out[n][nb] = g_i B[i][:]
+int beta_grad_blocks(int n);
+hipError_t launch_beta_grad(int n, int nb, const double *g, const double *B, int per_atom,
+                            double *part, double *out, hipStream_t s);
 
 // dst[e][atom][re/im] = scale[e] * src[map[e] * npad + atom] for atom < n
 hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const int *map,

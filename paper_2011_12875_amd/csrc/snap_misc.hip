@@ -204,6 +204,45 @@ __global__ void k_virial_sum(int nblk, const double *__restrict__ partial,
     out[k] = s;
 }
 
+// ---------------------------------------------------------------------------
+// dE/dbeta of the weighted energy sum_i g_i E_i with E_i = beta . B_i: the
+// sum over atoms of g_i B_i (shared coefficients) in two passes of fixed
+// order (per block of atoms, then over the blocks), or g_i B_i per atom
+// ---------------------------------------------------------------------------
+constexpr int kBetaGradAtoms = 256;
+
+__global__ __launch_bounds__(64) void k_beta_grad_part(int n, int nb, const double *__restrict__ g,
+                                                       const double *__restrict__ B,
+                                                       double *__restrict__ part)
+{
+    const int i0 = blockIdx.x * kBetaGradAtoms;
+    const int i1 = min(n, i0 + kBetaGradAtoms);
+    for (int l = threadIdx.x; l < nb; l += 64) {
+        double s = 0.0;
+        for (int i = i0; i < i1; ++i) s += g[i] * B[(size_t)i * nb + l];
+        part[(size_t)blockIdx.x * nb + l] = s;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_beta_grad_sum(int nblk, int nb,
+                                                      const double *__restrict__ part,
+                                                      double *__restrict__ out)
+{
+    const int l = blockIdx.x * 64 + threadIdx.x;
+    if (l >= nb) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nb + l];
+    out[l] = s;
+}
+
+__global__ void k_beta_grad_atom(long long total, int nb, const double *__restrict__ g,
+                                 const double *__restrict__ B, double *__restrict__ out)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    out[k] = g[k / nb] * B[k];
+}
+
 // dst[e][i] = scale[e] * src[map[e] * npad + i] (map, scale optional)
 __global__ void k_unscale(int n, int npad, int nhalf, const double2 *__restrict__ src,
                           const int *__restrict__ map, const double *__restrict__ scale,
@@ -266,6 +305,29 @@ hipError_t launch_virial(int n, const double *pos, const int *off, const int *nb
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_virial_sum, dim3(1), dim3(64), 0, s, nblk, partial, out);
+    return hipGetLastError();
+}
+
+int beta_grad_blocks(int n) { return (n + kBetaGradAtoms - 1) / kBetaGradAtoms; }
+
+hipError_t launch_beta_grad(int n, int nb, const double *g, const double *B, int per_atom,
+                            double *part, double *out, hipStream_t s)
+{
+    if (per_atom) {
+        const long long total = (long long)n * nb;
+        if (total == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_beta_grad_atom, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                           s, total, nb, g, B, out);
+        return hipGetLastError();
+    }
+    const int nblk = beta_grad_blocks(n);
+    if (nblk > 0) {
+        hipLaunchKernelGGL(k_beta_grad_part, dim3(nblk), dim3(64), 0, s, n, nb, g, B, part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_beta_grad_sum, dim3((nb + 63) / 64), dim3(64), 0, s, nblk, nb, part,
+                       out);
     return hipGetLastError();
 }
 

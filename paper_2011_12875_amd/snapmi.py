@@ -27,7 +27,8 @@ EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_n
            "snap_stage_times", "snap_sync_status", "snap_last_error",
            "snap_mlp_nparams", "snap_mlp_workspace", "snap_mlp_forward", "snap_mlp_grad",
            "snap_adam_step", "snap_jacobian", "snap_jacobian_forces", "snap_jacobian_adjoint",
-           "snap_fit_residuals", "snap_virial", "snap_set_elements", "snap_compute_elements"]
+           "snap_fit_residuals", "snap_virial", "snap_set_elements", "snap_compute_elements",
+           "snap_beta_grad"]
 
 
 class SnapError(RuntimeError):
@@ -69,7 +70,8 @@ def load():
         "snap_compute_elements": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "snap_forward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp]),
         "snap_backward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp]),
-        "snap_copy_workspace": (i, [vp, i, vp, vp]),
+        "snap_copy_workspace": (i, [vp, i, i, vp, vp]),
+        "snap_beta_grad": (i, [vp, i, vp, vp, i, vp, vp]),
         "snap_sync_status": (i, [vp, vp]),
         "snap_profile": (i, [vp, i]),
         "snap_stage_times": (i, [vp, dp, ip]),
@@ -369,11 +371,27 @@ class SnapPotential:
         return (W, Wa.reshape(n, 3, 3)) if per_atom else W
 
     def workspace(self, which, n):
-        """True U_j (which=0) or Y_j (which=1) of the last call: [nhalf, n] complex."""
+        """True U_j (which=0) or Y_j (which=1) of the last call: [nhalf, n]
+        complex; n must be that call's atom count (the library checks)."""
         import torch
-        dst = torch.empty((self.nhalf, n, 2), dtype=torch.float64, device="cuda")
-        _check(load().snap_copy_workspace(self._ctx, which, self._ptr(dst), self._stream()))
-        return torch.view_as_complex(dst)
+        dst = torch.empty((self.nhalf, max(int(n), 1), 2), dtype=torch.float64, device="cuda")
+        _check(load().snap_copy_workspace(self._ctx, which, int(n), self._ptr(dst),
+                                          self._stream()))
+        return torch.view_as_complex(dst[:, :n])
+
+    def beta_grad(self, grad_energy, bispectrum, per_atom=False):
+        """d(sum_i g_i E_i)/dbeta: sum_i g_i B_i [N_B], or g_i B_i [n, N_B]."""
+        import torch
+        g = grad_energy.contiguous()
+        n = g.shape[0]
+        assert g.dtype == torch.float64 and g.is_cuda and g.dim() == 1
+        assert bispectrum.dtype == torch.float64 and bispectrum.is_contiguous()
+        assert tuple(bispectrum.shape) == (n, self.ncoeff)
+        shape = (n, self.ncoeff) if per_atom else (self.ncoeff,)
+        out = torch.empty(shape, dtype=torch.float64, device=g.device)
+        _check(load().snap_beta_grad(self._ctx, n, self._ptr(g), self._ptr(bispectrum),
+                                     1 if per_atom else 0, self._ptr(out), self._stream()))
+        return out
 
     def sync_status(self):
         return _check(load().snap_sync_status(self._ctx, self._stream()))

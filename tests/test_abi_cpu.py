@@ -204,3 +204,42 @@ def test_neighbor_builder_orthorhombic_box():
     pos, box = wl.bcc((4, 5, 7), 0.1, 22)
     assert len(set(box.tolist())) == 3
     _same_lists(pos, box, wl.RCUT)
+
+
+@pytest.mark.parametrize("tj,limit", [(14, 8947840), (8, 14913024)])
+def test_sizes_beyond_the_row_addressing_limit_are_rejected(tj, limit):
+    """compute_Y addresses a row of U_J with 32-bit byte counts, so
+    16 (2J + 1) npad must stay below 2^31: larger n is refused on the host,
+    before any device work (no pointer is dereferenced)."""
+    lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.snap_setup(tj, wl.RCUT, wl.RFAC0, 0.0, 1, ctypes.byref(ctx)) == 0
+    assert 16 * (tj + 1) * limit < 2 ** 31 <= 16 * (tj + 1) * (limit + 64)
+    dummy = ctypes.c_void_p(256)
+    box = (ctypes.c_double * 3)(1e4, 1e4, 1e4)
+    for fn in ("snap_compute", "snap_forward", "snap_backward"):
+        f = getattr(lib, fn)
+        args = {"snap_compute": (ctx, limit + 1, 0, dummy, box, dummy, dummy, dummy, dummy, 0,
+                                 dummy, dummy, None, None, None),
+                "snap_forward": (ctx, limit + 1, 0, dummy, box, dummy, dummy, dummy, dummy, 0,
+                                 dummy, dummy, None),
+                "snap_backward": (ctx, limit + 1, 0, dummy, box, dummy, dummy, dummy, dummy, 0,
+                                  dummy, dummy, None, None)}[fn]
+        assert f(*args) == -1, fn
+        assert b"too large" in lib.snap_last_error(), fn
+    assert lib.snap_destroy(ctx) == 0
+
+
+def test_backward_without_forward_is_rejected():
+    """snap_backward reuses the U of a forward call on the same context; with
+    none it refuses on the host."""
+    lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.snap_setup(4, wl.RCUT, wl.RFAC0, 0.0, 1, ctypes.byref(ctx)) == 0
+    dummy = ctypes.c_void_p(256)
+    box = (ctypes.c_double * 3)(100.0, 100.0, 100.0)
+    assert lib.snap_backward(ctx, 10, 20, dummy, box, dummy, dummy, dummy, dummy, 0, dummy, dummy,
+                             None, None) == -1
+    assert b"snap_forward" in lib.snap_last_error()
+    assert lib.snap_copy_workspace(ctx, 0, 10, dummy, None) == -1
+    assert lib.snap_destroy(ctx) == 0

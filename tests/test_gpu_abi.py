@@ -1,0 +1,78 @@
+"""Call sequences of the C ABI on the GPU: a backward pass only runs on the
+U_j it was made for, helper calls between forward and backward leave that U
+alone, and copies of the workspace are sized by the caller's n."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2011_12875_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(ncell, seed, tj=4):
+    import torch
+    from paper_2011_12875_amd import snapmi
+    pos, box = wl.bcc(ncell, 0.1, seed)
+    pot = snapmi.SnapPotential(tj, wl.RCUT)
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    tpos = torch.as_tensor(pos, device="cuda")
+    tbeta = torch.as_tensor(wl.beta(wl.ncoeff(tj), seed + 1), device="cuda")
+    return torch, snapmi, pot, nl, pos, box, tpos, tbeta
+
+
+def test_backward_with_other_pair_count_is_rejected():
+    torch, snapmi, pot, nl, pos, box, tpos, tbeta = _setup(3, 60)
+    pot.forward(tpos, box, nl, tbeta)
+    wider = snapmi.NeighborList.build(pos, box, 5.5)  # a skin: more pairs, same atoms
+    assert wider.npairs > nl.npairs
+    g = torch.ones(len(pos), dtype=torch.float64, device="cuda")
+    with pytest.raises(snapmi.SnapError) as e:
+        pot.backward(tpos, box, wider, tbeta, g)
+    assert e.value.code == -1
+    F = pot.backward(tpos, box, nl, tbeta, g)  # the matching list still works
+    o = oracle.snap(pos, box, 4, wl.RCUT, beta=tbeta.cpu().numpy(), want_dE=False)
+    assert np.abs(F.cpu().numpy() - o["F"]).max() <= 1e-10
+
+
+def test_backward_after_workspace_growth_is_rejected():
+    """A larger call in between regrows (and clears) U: the backward of the
+    earlier forward must refuse, not run on the cleared U."""
+    torch, snapmi, pot, nl, pos, box, tpos, tbeta = _setup(3, 62)
+    pos2, box2 = wl.bcc(5, 0.1, 63)
+    nl2 = snapmi.NeighborList.build(pos2, box2, wl.RCUT)
+    pot.forward(tpos, box, nl, tbeta)
+    pot.compute(torch.as_tensor(pos2, device="cuda"), box2, nl2, tbeta)
+    g = torch.ones(len(pos), dtype=torch.float64, device="cuda")
+    with pytest.raises(snapmi.SnapError):
+        pot.backward(tpos, box, nl, tbeta, g)
+    # a fresh forward makes it valid again (the workspace is large enough now)
+    pot.forward(tpos, box, nl, tbeta)
+    F = pot.backward(tpos, box, nl, tbeta, g)
+    o = oracle.snap(pos, box, 4, wl.RCUT, beta=tbeta.cpu().numpy(), want_dE=False)
+    assert np.abs(F.cpu().numpy() - o["F"]).max() <= 1e-10
+
+
+def test_virial_between_forward_and_backward_keeps_u():
+    """snap_virial of a larger system between a forward and its backward has
+    its own partial-sum buffer: the backward still gives the oracle's forces."""
+    torch, snapmi, pot, nl, pos, box, tpos, tbeta = _setup(3, 64)
+    pos2, box2 = wl.bcc(6, 0.1, 65)
+    nl2 = snapmi.NeighborList.build(pos2, box2, wl.RCUT)
+    pot.forward(tpos, box, nl, tbeta)
+    dE2 = torch.zeros((nl2.npairs, 3), dtype=torch.float64, device="cuda")
+    pot.virial(torch.as_tensor(pos2, device="cuda"), box2, nl2, dE2)
+    g = torch.ones(len(pos), dtype=torch.float64, device="cuda")
+    F = pot.backward(tpos, box, nl, tbeta, g)
+    o = oracle.snap(pos, box, 4, wl.RCUT, beta=tbeta.cpu().numpy(), want_dE=False)
+    assert np.abs(F.cpu().numpy() - o["F"]).max() <= 1e-10
+
+
+def test_workspace_copy_checks_n():
+    torch, snapmi, pot, nl, pos, box, tpos, tbeta = _setup(3, 66)
+    pot.compute(tpos, box, nl, tbeta)
+    for bad in (len(pos) - 1, len(pos) + 64):
+        with pytest.raises(snapmi.SnapError):
+            pot.workspace(0, bad)
+    U = pot.workspace(0, len(pos))
+    assert U.shape == (pot.nhalf, len(pos))

@@ -107,3 +107,41 @@ def test_backward_after_intervening_call():
     E.sum().backward()
     o = oracle.snap(pos, box, tj, wl.RCUT, beta=beta, want_dE=False)
     assert np.abs(-tpos.grad.cpu().numpy() - o["F"]).max() <= 1e-10
+
+
+def test_per_atom_beta_gradient_and_determinism():
+    """Per-atom coefficients: dL/dbeta_i = g_i B_i; shared coefficients: the
+    fixed-order reduction gives bit-identical repeats."""
+    torch, pot, nl, pos, box, beta, tj = _setup("bcc128_2j4")
+    from paper_2011_12875_amd.autograd import snap_energy
+    g = np.random.default_rng(9).normal(size=len(pos))
+    bat = np.tile(beta, (len(pos), 1)) * (1.0 + 0.1 * np.random.default_rng(10).normal(
+        size=(len(pos), 1)))
+    tpos = torch.tensor(pos, device="cuda", requires_grad=True)
+    tb = torch.tensor(bat, device="cuda", requires_grad=True)
+    E = snap_energy(tpos, tb, pot, box, nl)
+    (E * torch.tensor(g, device="cuda")).sum().backward()
+    ob = oracle.snap(pos, box, tj, wl.RCUT, beta=bat, want_dE=False)
+    ref = g[:, None] * ob["B"]
+    assert np.abs(tb.grad.cpu().numpy() - ref).max() <= 1e-11 * np.abs(ref).max()
+    o = oracle.snap(pos, box, tj, wl.RCUT, beta=g[:, None] * bat, want_dE=False)
+    assert np.abs(-tpos.grad.cpu().numpy() - o["F"]).max() <= 1e-10
+    gt = torch.tensor(g, device="cuda")
+    B = torch.tensor(ob["B"], device="cuda")
+    r1 = pot.beta_grad(gt, B).cpu().numpy()
+    r2 = pot.beta_grad(gt, B).cpu().numpy()
+    assert np.array_equal(r1, r2)
+    assert np.abs(r1 - g @ ob["B"]).max() <= 1e-12 * np.abs(g @ ob["B"]).max()
+
+
+def test_double_backward_raises():
+    """The adjoint is once-differentiable: a second derivative through it
+    raises instead of silently returning a gradient without a graph."""
+    torch, pot, nl, pos, box, beta, tj = _setup("bcc128_2j4")
+    from paper_2011_12875_amd.autograd import snap_energy
+    tpos = torch.tensor(pos, device="cuda", requires_grad=True)
+    tbeta = torch.tensor(beta, device="cuda")
+    E = snap_energy(tpos, tbeta, pot, box, nl)
+    (gpos,) = torch.autograd.grad(E.sum(), tpos, create_graph=True)
+    with pytest.raises(RuntimeError):
+        torch.autograd.grad(gpos.pow(2).sum(), tpos)
