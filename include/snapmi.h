@@ -144,6 +144,23 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
                  int per_atom_beta, double *energy, double *force, double *bispec,
                  double *dE_pair, void *stream);
 
+/* Quadratic SNAP: the energy of eq. (snapatomenergy) extended to second
+ * order in the bispectrum,
+ *   E_i = beta . B_i + (1/2) B_i^T alpha B_i,
+ * with forces from the adjoint stages run with the per-atom coefficients
+ * g_i = dE_i/dB_i = beta + (1/2)(alpha + alpha^T) B_i (Sec. IV: Y takes any
+ * per-atom coefficient vector, so any E_i = f(B_i) gets its forces this way).
+ *   beta  dev double[N_B];  alpha dev double[N_B][N_B] (row-major; only its
+ *         symmetric part matters)
+ * Other arguments, outputs and errors as snap_compute (energy is the
+ * quadratic E_i; bispec, if not NULL, receives B_i).  Stages: compute_U,
+ * bispectrum, the energy and g_i, compute_Y, compute_dE, update_forces.  The
+ * U_j of the call are kept as by snap_compute. */
+int snap_compute_quadratic(snap_ctx *c, int n, int npairs, const double *pos,
+                           const double box[3], const int *off, const int *nbr, const int *rev,
+                           const double *beta, const double *alpha, double *energy,
+                           double *force, double *bispec, double *dE_pair, void *stream);
+
 /* Several elements (the density weights and per-element radii that
  * Sec. II.A leaves out of eq. (u), deferring to the SNAP reference it
  * cites).  Element e has radius[e] > 0 and density weight weight[e]; the pair

@@ -225,6 +225,31 @@ def snap_elements(pos, box, twojmax, types, radius, weight, rcutfac, beta, rfac0
     return out
 
 
+def snap_quadratic(pos, box, twojmax, rcut, beta, alpha, rfac0=0.99363, rmin0=0.0,
+                   switch_flag=1, wself=1.0, nthreads=0):
+    """Quadratic SNAP: E_i = beta . B_i + (1/2) B_i^T alpha B_i, the quadratic
+    extension of eq. (snapatomenergy) in the bispectrum (Sec. II.A writes the
+    energy as a function of B_i; this is its second-order form).
+
+    By the chain rule dE_i/dr = g_i . dB_i/dr with g_i = dE_i/dB_i =
+    beta + (1/2)(alpha + alpha^T) B_i, so the forces and pair derivatives are
+    those of the oracle's literal dB/dr route with the per-atom coefficients
+    g_i.  Returns the dict of :func:`snap` with E replaced by the quadratic
+    energy and ``G`` = g_i [n, N_B]."""
+    beta = np.asarray(beta, dtype=np.float64)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    nb = len(beta)
+    assert alpha.shape == (nb, nb)
+    kw = dict(rfac0=rfac0, rmin0=rmin0, switch_flag=switch_flag, wself=wself, nthreads=nthreads)
+    B = snap(pos, box, twojmax, rcut, beta=beta, want_dE=False, **kw)["B"]
+    E = B @ beta + 0.5 * np.einsum("il,lm,im->i", B, alpha, B)
+    G = beta[None, :] + B @ (0.5 * (alpha + alpha.T)).T
+    out = snap(pos, box, twojmax, rcut, beta=np.ascontiguousarray(G), **kw)
+    out["E"] = E
+    out["G"] = G
+    return out
+
+
 def max_threads() -> int:
     return _load().oracle_max_threads()
 

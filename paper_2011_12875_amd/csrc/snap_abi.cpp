@@ -47,6 +47,9 @@ struct snap_ctx {
     // buffer: growing it never touches U)
     double *part = nullptr;
     size_t cap_part = 0;
+    // quadratic SNAP: bispectra and per-atom coefficients, [cap_quad][N_B] each
+    double *qB = nullptr, *qG = nullptr;
+    int cap_quad = 0;
     // stage timing (snap_profile): event pairs recorded per stage
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -152,6 +155,10 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(c->part);
     c->part = nullptr;
     c->cap_part = 0;
+    (void)hipFree(c->qB);
+    (void)hipFree(c->qG);
+    c->qB = c->qG = nullptr;
+    c->cap_quad = 0;
     c->elem_dirty = c->nelem > 0;
     c->dev_ready = false;
     c->cap_atoms = c->cap_pairs = 0;
@@ -247,6 +254,22 @@ static int ensure_part(snap_ctx *c, size_t doubles, hipStream_t s)
     c->cap_part = 0;
     HIP_TRY(hipMalloc((void **)&c->part, sizeof(double) * doubles), "alloc partial sums");
     c->cap_part = doubles;
+    return SNAP_OK;
+}
+
+// Grow the quadratic-SNAP buffers to n atoms.
+static int ensure_quad(snap_ctx *c, int n, hipStream_t s)
+{
+    if (n <= c->cap_quad) return SNAP_OK;
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    (void)hipFree(c->qB);
+    (void)hipFree(c->qG);
+    c->qB = c->qG = nullptr;
+    c->cap_quad = 0;
+    const size_t bytes = sizeof(double) * (size_t)n * c->tab.nb;
+    HIP_TRY(hipMalloc((void **)&c->qB, bytes), "alloc quadratic bispectra");
+    HIP_TRY(hipMalloc((void **)&c->qG, bytes), "alloc quadratic coefficients");
+    c->cap_quad = n;
     return SNAP_OK;
 }
 
@@ -561,6 +584,63 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
 {
     return compute_impl(c, n, npairs, pos, box, off, nbr, rev, nullptr, beta, per_atom_beta,
                         energy, force, bispec, dE_pair, stream);
+}
+
+int snap_compute_quadratic(snap_ctx *c, int n, int npairs, const double *pos,
+                           const double box[3], const int *off, const int *nbr, const int *rev,
+                           const double *beta, const double *alpha, double *energy,
+                           double *force, double *bispec, double *dE_pair, void *stream)
+{
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
+    if (st) return st;
+    if (n > 0 && (!energy || !force || !alpha)) return fail(SNAP_EINVAL, "NULL pointer argument");
+    if ((st = ensure_device(c))) return st;
+    if (n == 0) return SNAP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_work(c, n, npairs > 0 ? npairs : 1, s))) return st;
+    if ((st = ensure_quad(c, n, s))) return st;
+    const Geom g = make_geom(c, box);
+    Work &w = c->work;
+    const int nb = c->tab.nb;
+    double *B = bispec ? bispec : c->qB;
+    double *dE = dE_pair ? dE_pair : w.dE;
+    {
+        StageTimer tm(c, 0, s);
+        if ((st = run_u(c, n, npairs, pos, g, off, nbr, s))) return st;
+        tm.finish();
+    }
+    {
+        StageTimer tm(c, 4, s);
+        HIP_TRY(launch_bispectrum(n, w.npad, w.U, c->dev, nb, B, nullptr, 0, nullptr, s,
+                                  c->tab.nfullel),
+                "bispectrum launch");
+        HIP_TRY(launch_quadratic(n, nb, B, beta, alpha, energy, c->qG, s), "quadratic launch");
+        tm.finish();
+    }
+    {
+        // Y from the per-atom coefficients g_i = dE_i/dB_i (Sec. IV: the
+        // adjoint takes any per-atom coefficient vector)
+        StageTimer tm(c, 1, s);
+        HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, c->qG, 1, nb,
+                                 nullptr, 0, nullptr, nullptr, s),
+                "compute_Y launch");
+        tm.finish();
+    }
+    if (npairs > 0) {
+        StageTimer tm(c, 2, s);
+        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
+                            w.Y, c->dev, g, dE, s),
+                "compute_dE launch");
+        tm.finish();
+    }
+    {
+        StageTimer tm(c, 3, s);
+        HIP_TRY(launch_gather(n, w.npad, c->dev.nyrows, off, rev, dE, nullptr, nullptr, force, s),
+                "update_forces launch");
+        tm.finish();
+    }
+    record_forward(c, n, npairs);
+    return SNAP_OK;
 }
 
 int snap_set_elements(snap_ctx *c, int nelem, const double *radius, const double *weight,

@@ -89,6 +89,11 @@ hipError_t launch_virial(int n, const double *pos, const int *off, const int *nb
                          const double *dE, double *watom, double *partial, double *out,
                          hipStream_t s);
 
+// quadratic SNAP: energy[n] = beta . B_i + B_i^T alpha B_i / 2 and
+// g[n][nb] = beta + (alpha + alpha^T) B_i / 2 (B [n][nb], alpha [nb][nb])
+hipError_t launch_quadratic(int n, int nb, const double *B, const double *beta,
+                            const double *alpha, double *energy, double *g, hipStream_t s);
+
 // dE/dbeta of sum_i g_i E_i: out[nb] = sum_i g_i B[i][:] in a fixed order
 // (part: beta_grad_blocks(n) * nb doubles), or out[n][nb] = g_i B[i][:]
 int beta_grad_blocks(int n);

@@ -205,6 +205,40 @@ __global__ void k_virial_sum(int nblk, const double *__restrict__ partial,
 }
 
 // ---------------------------------------------------------------------------
+// quadratic SNAP: E_i = beta . B_i + (1/2) B_i^T alpha B_i and the per-atom
+// coefficients of its forces, g_i = dE_i/dB_i = beta + (1/2)(alpha + alpha^T) B_i.
+// Lane per atom; the block's 64 bispectra are staged in LDS transposed
+// ([component][atom]), alpha and beta are read with wavefront-uniform loads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_quadratic(int n, int nb, const double *__restrict__ B,
+                                                  const double *__restrict__ beta,
+                                                  const double *__restrict__ alpha,
+                                                  double *__restrict__ energy,
+                                                  double *__restrict__ g)
+{
+    extern __shared__ double qs[];  // [nb][64]
+    const int lane = threadIdx.x;
+    const int i0 = blockIdx.x * 64;
+    const int na = min(64, n - i0);
+    // the block's rows of B are one contiguous run of na * nb doubles
+    for (int k = lane; k < 64 * nb; k += 64) {
+        const int a = k / nb, l = k - a * nb;
+        qs[l * 64 + a] = a < na ? B[(size_t)i0 * nb + k] : 0.0;
+    }
+    __syncthreads();
+    const int i = i0 + lane;
+    double e = 0.0;
+    for (int l = 0; l < nb; ++l) {
+        double sl = 0.0;
+        for (int m = 0; m < nb; ++m)
+            sl += 0.5 * (alpha[(size_t)l * nb + m] + alpha[(size_t)m * nb + l]) * qs[m * 64 + lane];
+        e += (beta[l] + 0.5 * sl) * qs[l * 64 + lane];
+        if (lane < na) g[(size_t)i * nb + l] = beta[l] + sl;
+    }
+    if (lane < na) energy[i] = e;
+}
+
+// ---------------------------------------------------------------------------
 // dE/dbeta of the weighted energy sum_i g_i E_i with E_i = beta . B_i: the
 // sum over atoms of g_i B_i (shared coefficients) in two passes of fixed
 // order (per block of atoms, then over the blocks), or g_i B_i per atom
@@ -305,6 +339,27 @@ hipError_t launch_virial(int n, const double *pos, const int *off, const int *nb
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_virial_sum, dim3(1), dim3(64), 0, s, nblk, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_quadratic(int n, int nb, const double *B, const double *beta,
+                            const double *alpha, double *energy, double *g, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * 64 * (size_t)nb;
+    if (lds > 64 * 1024) {
+        // beyond the default dynamic LDS limit (2J >= 11): raise it once
+        static bool raised = false;
+        if (!raised) {
+            const hipError_t e = hipFuncSetAttribute((const void *)k_quadratic,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)lds);
+            if (e != hipSuccess) return e;
+            raised = true;
+        }
+    }
+    hipLaunchKernelGGL(k_quadratic, dim3((n + 63) / 64), dim3(64), lds, s, n, nb, B, beta, alpha,
+                       energy, g);
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_n
            "snap_mlp_nparams", "snap_mlp_workspace", "snap_mlp_forward", "snap_mlp_grad",
            "snap_adam_step", "snap_jacobian", "snap_jacobian_forces", "snap_jacobian_adjoint",
            "snap_fit_residuals", "snap_virial", "snap_set_elements", "snap_compute_elements",
-           "snap_beta_grad"]
+           "snap_beta_grad", "snap_compute_quadratic"]
 
 
 class SnapError(RuntimeError):
@@ -72,6 +72,8 @@ def load():
         "snap_backward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp]),
         "snap_copy_workspace": (i, [vp, i, i, vp, vp]),
         "snap_beta_grad": (i, [vp, i, vp, vp, i, vp, vp]),
+        "snap_compute_quadratic": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                       vp]),
         "snap_sync_status": (i, [vp, vp]),
         "snap_profile": (i, [vp, i]),
         "snap_stage_times": (i, [vp, dp, ip]),
@@ -258,6 +260,31 @@ class SnapPotential:
             self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
             self._stream()))
         self._fwd_token += 1  # U of this call replaces that of the last forward
+        return out
+
+    def compute_quadratic(self, pos, box, nl, beta, alpha, bispectrum=False, pair_derivs=False,
+                          out=None):
+        """Quadratic SNAP, E_i = beta . B_i + B_i^T alpha B_i / 2: E_i and F_i
+        (optionally B_i and dE per pair).  beta [N_B], alpha [N_B, N_B]."""
+        import torch
+        n, boxa, per_atom = self._args(pos, box, nl, beta)
+        assert not per_atom
+        assert alpha.dtype == torch.float64 and alpha.is_cuda and alpha.is_contiguous()
+        assert tuple(alpha.shape) == (self.ncoeff, self.ncoeff)
+        dev = pos.device
+        if out is None:
+            out = {"energy": torch.empty(n, dtype=torch.float64, device=dev),
+                   "force": torch.empty((n, 3), dtype=torch.float64, device=dev)}
+            if bispectrum:
+                out["bispectrum"] = torch.empty((n, self.ncoeff), dtype=torch.float64, device=dev)
+            if pair_derivs:
+                out["dE"] = torch.empty((max(nl.npairs, 1), 3), dtype=torch.float64, device=dev)
+        _check(load().snap_compute_quadratic(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(beta), self._ptr(alpha), self._ptr(out["energy"]),
+            self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
+            self._stream()))
+        self._fwd_token += 1
         return out
 
     def set_elements(self, radius, weight, rcutfac):

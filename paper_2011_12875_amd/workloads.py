@@ -76,6 +76,14 @@ def beta(ncoeff: int, seed: int, sd: float = 0.1, natoms: int | None = None):
     return rng.normal(0.0, sd, size=shape)
 
 
+def quadratic_alpha(ncoeff: int, seed: int, scale: float = 1e-4):
+    """Synthetic quadratic coefficients: scale (G + G^T)/2 with G ~ N(0, 1)
+    (symmetric, [ncoeff, ncoeff]).  With bispectra of rms ~40 at the BCC
+    workloads, 1e-4 makes the quadratic energy comparable to the linear one."""
+    g = np.random.default_rng(seed).normal(0.0, 1.0, size=(ncoeff, ncoeff))
+    return scale * 0.5 * (g + g.T)
+
+
 def ncoeff(twojmax: int) -> int:
     """Number of bispectrum components for a given twojmax (counting only)."""
     n = 0

@@ -118,38 +118,106 @@ def test_all_twojmax_small(tj):
     assert (np.abs(g["bispectrum"] - o["B"]) / bscale).max() <= E_REL
 
 
-def test_2j14_sampled():
-    """2J=14 at the benchmark size: exact oracle values on a sample of
-    centres (energies, bispectra) and of atoms whose whole neighbourhood is
-    evaluated (forces)."""
+def _full_check(pos, box, beta, tj, label, ocall=None, **kw):
+    """E, B and F of every atom and dE of every pair against the oracle."""
+    print("case", label, flush=True)
+    g = _run(pos, box, beta, tj, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("rcut", "rfac0", "rmin0", "switch_flag", "wself")}
+    rcut = okw.pop("rcut", wl.RCUT)
+    o = ocall() if ocall else oracle.snap(pos, box, tj, rcut, beta=beta, **okw)
+    _check_energy(g["energy"], o["E"])
+    assert np.abs(g["force"] - o["F"]).max() <= F_ABS
+    bscale = np.maximum(np.abs(o["B"]), 1.0)
+    assert (np.abs(g["bispectrum"] - o["B"]) / bscale).max() <= E_REL
+    om = _pair_map(o["off"], o["nbr"])
+    gm = _pair_map(g["off"], g["nbr"])
+    for key, t in gm.items():   # listed pairs the oracle leaves out contribute nothing
+        if key not in om:
+            assert np.all(g["dE"][t] == 0.0), key
+    go = np.array([gm[k] for k in om], dtype=np.int64)
+    oo = np.array([om[k] for k in om], dtype=np.int64)
+    if len(oo):
+        assert np.abs(g["dE"][go] - o["dE"][oo]).max() <= F_ABS
+    return g, o
+
+
+def test_2j14_full():
+    """2J = 14 (204 components) at the benchmark size: every atom and pair."""
     pos, box, beta, tj = _full("bcc2000_2j14")
-    g = _run(pos, box, beta, tj, want_de=False)
-    rng = np.random.default_rng(0)
-    off, nbr = g["off"], g["nbr"]
-    ks = rng.choice(len(pos), 3, replace=False)
-    centres = np.unique(np.concatenate([np.concatenate([[k], nbr[off[k]:off[k + 1]]]) for k in ks]))
-    o = oracle.snap(pos, box, tj, wl.RCUT, beta=beta, centers=centres, want_dE=False)
-    _check_energy(g["energy"], o["E"], centres)
-    bscale = np.maximum(np.abs(o["B"][centres]), 1.0)
-    assert (np.abs(g["bispectrum"][centres] - o["B"][centres]) / bscale).max() <= E_REL
-    assert np.abs(g["force"][ks] - o["F"][ks]).max() <= F_ABS
+    _full_check(pos, box, beta, tj, "bcc2000_2j14")
 
 
-def test_uneven_neighbours_sampled():
-    """15 200 atoms with vacancies (16-30 neighbours) in one launch."""
+def test_uneven_neighbours_full():
+    """15 200 atoms with vacancies (16-30 neighbours) in one launch: every
+    atom and pair (several blocks per XCD in compute_Y's walk)."""
     pos, box, beta, tj = _full("bcc15200vac_2j8")
-    g = _run(pos, box, beta, tj, want_b=False, want_de=False)
+    g, _ = _full_check(pos, box, beta, tj, "bcc15200vac_2j8")
     counts = np.diff(g["off"])
     assert counts.min() <= 20 and counts.max() >= 28
-    off, nbr = g["off"], g["nbr"]
-    ks = np.concatenate([[int(np.argmin(counts)), int(np.argmax(counts)), len(pos) - 1],
-                         np.random.default_rng(1).choice(len(pos), 5, replace=False)])
-    centres = np.unique(np.concatenate([np.concatenate([[k], nbr[off[k]:off[k + 1]]]) for k in ks]))
-    o = oracle.snap(pos, box, tj, wl.RCUT, beta=beta, centers=centres, want_dE=False)
-    _check_energy(g["energy"], o["E"], centres)
-    assert np.abs(g["force"][ks] - o["F"][ks]).max() <= F_ABS
-    # properties that hold at any size
     assert np.abs(g["force"].sum(0)).max() < 1e-8
+
+
+@pytest.mark.parametrize("tj", [4, 8])
+def test_inner_radius(tj):
+    """rmin0 = 2.9 A between the first and second BCC shells: pairs on both
+    sides of the inner radius (f_c = 1 inside, theta0 offset)."""
+    pos, box = wl.bcc(4, 0.1, 70 + tj)
+    beta = wl.beta(wl.ncoeff(tj), 71 + tj)
+    _full_check(pos, box, beta, tj, "rmin0 2.9 twojmax %d" % tj, rmin0=2.9)
+
+
+def test_strict_cutoff_without_switching():
+    """Switching off (f_c = 1 up to rcut): neighbours at rcut (1 - 1e-12)
+    count, at rcut (1 + 1e-12) they do not, also when the list holds them
+    (built to a longer cutoff, a skin)."""
+    torch = _torch()
+    from paper_2011_12875_amd import snapmi
+    rng = np.random.default_rng(75)
+    tj = 6
+    beta = wl.beta(wl.ncoeff(tj), 76)
+    dirs = rng.normal(size=(6, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    rc = wl.RCUT
+    pos = np.concatenate([np.zeros((1, 3)),
+                          rc * (1 - 1e-12) * dirs[:3], rc * (1 + 1e-12) * dirs[3:]])
+    pos = np.concatenate([pos, pos + np.array([30.0, 0.0, 0.0])])
+    pos[7:] += rng.normal(0.0, 0.3, size=(7, 3))   # a second, distorted copy
+    box = np.zeros(3)
+    g, o = _full_check(pos, box, beta, tj, "switching off at rcut", switch_flag=0)
+    assert np.diff(o["off"])[0] == 3
+    # the same system with a skin: pairs beyond rcut listed, still no contribution
+    pot = _pot(tj, switch_flag=0)
+    nl = snapmi.NeighborList.build(pos, box, rc + 0.5)
+    assert nl.npairs > len(o["nbr"])
+    out = pot.compute(torch.as_tensor(pos, device="cuda"), box, nl,
+                      torch.as_tensor(beta, device="cuda"), pair_derivs=True)
+    pot.sync_status()
+    _check_energy(out["energy"].cpu().numpy(), o["E"])
+    assert np.abs(out["force"].cpu().numpy() - o["F"]).max() <= F_ABS
+
+
+def test_orthorhombic_box():
+    """Three different periodic edges."""
+    pos, box = wl.bcc((4, 5, 6), 0.1, 77)
+    tj = 6
+    _full_check(pos, box, wl.beta(wl.ncoeff(tj), 78), tj, "orthorhombic 4x5x6")
+
+
+@pytest.mark.parametrize("open_axes", [(2,), (0, 1)])
+def test_partly_open_box(open_axes):
+    """A slab (z open) and a wire (x, y open): surfaces with fewer neighbours."""
+    pos, box = wl.bcc((5, 4, 6), 0.1, 79, open_axes=open_axes)
+    tj = 6
+    g, _ = _full_check(pos, box, wl.beta(wl.ncoeff(tj), 80), tj, "open axes %s" % (open_axes,))
+    assert np.diff(g["off"]).min() < 20
+
+
+def test_wide_open_cluster():
+    """An open cluster several cut-offs wide (each open axis holds more than
+    two cells of the neighbour builder)."""
+    pos, box = wl.cluster(300, 9.0, 0)
+    tj = 6
+    _full_check(pos, box, wl.beta(wl.ncoeff(tj), 81), tj, "cluster 300 atoms radius 9 A")
 
 
 def test_many_neighbours_and_open_box():
