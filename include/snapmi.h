@@ -68,6 +68,9 @@ typedef struct {
     double wself;      /* self weight on the diagonal of every U_j (1.0)     */
     int dedr_dirs;     /* directions per lane in compute_dE: 1 or 3 (0: auto,
                         * 3 up to 2J = 6, 1 above)                            */
+    int y_kernel;      /* compute_Y variant: 0 auto (the measured faster: rows
+                        * through the texture path), 1 rows through the texture
+                        * path, 2 U staged in LDS (2 <= 2J <= 8, else as 1)  */
 } snap_params;
 
 /* Create a context for one parameter set.  Builds the host index tables

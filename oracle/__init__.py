@@ -64,6 +64,11 @@ def _load():
             ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             ctypes.c_double, ctypes.c_int, ip, dp, dp, ctypes.c_double, dp, ctypes.c_int,
             ip, ip, ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.oracle_snap_list.restype = ctypes.c_int
+        lib.oracle_snap_list.argtypes = [
+            ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int,
+            ip, ip, dp, dp, dp, dp]
         lib.oracle_max_threads.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         _lib = lib
@@ -223,6 +228,33 @@ def snap_elements(pos, box, twojmax, types, radius, weight, rcutfac, beta, rfac0
     if want_utot:
         out["U"] = U[..., 0] + 1j * U[..., 1]
     return out
+
+
+def snap_on_list(pos, box, twojmax, rcut, off, nbr, beta, rfac0=0.99363, rmin0=0.0,
+                 switch_flag=1, wself=1.0, centers=None, nthreads=0):
+    """:func:`snap` on a neighbour list from :func:`neighbors` (same rcut),
+    so that the evaluation is timed without the brute-force search.  Returns
+    E, F, B (no dE)."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr if len(nbr) else np.zeros(1), dtype=np.int32)
+    n = pos.shape[0]
+    nb = lib.oracle_components(twojmax, None)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    per_atom = 1 if beta.ndim == 2 else 0
+    cen = None if centers is None else np.ascontiguousarray(centers, dtype=np.int32)
+    E = np.zeros(n)
+    F = np.zeros((n, 3))
+    B = np.zeros((n, max(nb, 1)))
+    st = lib.oracle_snap_list(n, _dp(pos), _dp(box), twojmax, rcut, rfac0, rmin0,
+                              int(switch_flag), wself, _dp(beta), per_atom,
+                              0 if cen is None else len(cen), _ip(cen), int(nthreads), _ip(off),
+                              _ip(nbr), _dp(E), _dp(F), _dp(B), None)
+    if st < 0:
+        raise RuntimeError("oracle_snap_list failed with status %d" % st)
+    return dict(E=E, F=F, B=B[:, :nb])
 
 
 def snap_quadratic(pos, box, twojmax, rcut, beta, alpha, rfac0=0.99363, rmin0=0.0,

@@ -353,14 +353,17 @@ static void pair_cut(const oelem *el, double rcut, int i, int k, double *rc, dou
     *w = el->weight[el->type[k]];
 }
 
+/* given_list: off/nbr already hold a full neighbour list of off[n] pairs
+ * (the brute-force one of oracle_neighbors, built beforehand); otherwise it
+ * is built here. */
 static int snap_eval(int n, const double *pos, const double box[3], int twojmax, double rcut,
                      double rfac0, double rmin0, int switch_flag, double wself, const oelem *el,
                      const double *beta, int per_atom_beta, int ncenter, const int *centers,
-                     int nthreads, int *off, int *nbr, int pair_cap, double *E, double *F,
-                     double *B, double *Utot, double *dE)
+                     int nthreads, int given_list, int *off, int *nbr, int pair_cap, double *E,
+                     double *F, double *B, double *Utot, double *dE)
 {
     if (n < 0 || twojmax < 0 || twojmax > ORACLE_MAXJ || rcut <= 0.0) return -1;
-    const int np = oracle_neighbors(n, pos, box, rcut, off, nbr, pair_cap);
+    const int np = given_list ? off[n] : oracle_neighbors(n, pos, box, rcut, off, nbr, pair_cap);
     if (np < 0) return -2;
 
     oparams P = {rcut, rfac0, rmin0, wself, switch_flag};
@@ -383,10 +386,11 @@ static int snap_eval(int n, const double *pos, const double box[3], int twojmax,
                     }
 
     const int ncent = centers ? ncenter : n;
+    /* thread count of this call only (a num_threads clause, no change to
+     * the process-wide default) */
     int nthr = 1;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-    nthr = omp_get_max_threads();
+    nthr = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
     (void)nthreads;
     double *Fthr = NULL;
@@ -396,7 +400,7 @@ static int snap_eval(int n, const double *pos, const double box[3], int twojmax,
     }
     int status = np;
 
-#pragma omp parallel
+#pragma omp parallel num_threads(nthr)
     {
         int tid = 0;
 #ifdef _OPENMP
@@ -567,8 +571,23 @@ int oracle_snap(int n, const double *pos, const double box[3], int twojmax, doub
                 int *nbr, int pair_cap, double *E, double *F, double *B, double *Utot, double *dE)
 {
     return snap_eval(n, pos, box, twojmax, rcut, rfac0, rmin0, switch_flag, wself, NULL, beta,
-                     per_atom_beta, ncenter, centers, nthreads, off, nbr, pair_cap, E, F, B, Utot,
-                     dE);
+                     per_atom_beta, ncenter, centers, nthreads, 0, off, nbr, pair_cap, E, F, B,
+                     Utot, dE);
+}
+
+/*
+ * oracle_snap_list: oracle_snap on a neighbour list built beforehand by
+ * oracle_neighbors with the same rcut (off[n+1], nbr[off[n]], inputs here),
+ * so that the evaluation can be timed apart from the brute-force search.
+ */
+int oracle_snap_list(int n, const double *pos, const double box[3], int twojmax, double rcut,
+                     double rfac0, double rmin0, int switch_flag, double wself, const double *beta,
+                     int per_atom_beta, int ncenter, const int *centers, int nthreads,
+                     const int *off, const int *nbr, double *E, double *F, double *B, double *dE)
+{
+    return snap_eval(n, pos, box, twojmax, rcut, rfac0, rmin0, switch_flag, wself, NULL, beta,
+                     per_atom_beta, ncenter, centers, nthreads, 1, (int *)off, (int *)nbr,
+                     off[n], E, F, B, NULL, dE);
 }
 
 /*
@@ -595,7 +614,7 @@ int oracle_snap_elements(int n, const double *pos, const double box[3], int twoj
         if (type[i] < 0 || type[i] >= nelem) return -1;
     const oelem el = {nelem, type, radius, weight, rcutfac};
     return snap_eval(n, pos, box, twojmax, 2.0 * rcutfac * rmax, rfac0, rmin0, switch_flag, wself,
-                     &el, beta, 0, 0, NULL, nthreads, off, nbr, pair_cap, E, F, B, Utot, dE);
+                     &el, beta, 0, 0, NULL, nthreads, 0, off, nbr, pair_cap, E, F, B, Utot, dE);
 }
 
 int oracle_max_threads(void)

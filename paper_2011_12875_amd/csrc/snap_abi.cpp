@@ -140,6 +140,10 @@ static void free_dev(snap_ctx *c)
     (void)hipFree(d.ycq);
     (void)hipFree(d.nfull);
     (void)hipFree(d.onehot);
+    (void)hipFree(d.ylcontrib);
+    (void)hipFree(d.ylcp);
+    (void)hipFree(d.yltask);
+    (void)hipFree(d.ylgroup);
     d = DevTables();
     Work &w = c->work;
     (void)hipFree(w.U);
@@ -193,6 +197,20 @@ static int ensure_device(snap_ctx *c)
         HIP_TRY(upload(d.onehot, eye), "upload unit coefficient vectors");
     }
     d.nyrows = (int)t.yrows.size();
+    if (!t.ylcontrib.empty() && c->prm.y_kernel != 1) {
+        HIP_TRY(upload(d.ylcontrib, t.ylcontrib), "upload ylcontrib");
+        HIP_TRY(upload(d.ylcp, t.ylcp), "upload ylcp");
+        HIP_TRY(upload(d.yltask, t.yltask), "upload yltask");
+        HIP_TRY(upload(d.ylgroup, t.ylgroup), "upload ylgroup");
+        for (int gi = 0; gi < kYLdsGroupings; ++gi) {
+            d.yl_task_off[gi] = t.yl_task_off[gi];
+            d.yl_group_off[gi] = t.yl_group_off[gi];
+        }
+        d.yl_cost_total = 0;
+        for (long x : t.yl_cost) d.yl_cost_total += x;
+        d.y_lds = true;
+        d.y_lds_selected = c->prm.y_kernel == 2;
+    }
     HIP_TRY(hipMalloc((void **)&c->work.flag, sizeof(int)), "alloc flag");
     HIP_TRY(hipMemset(c->work.flag, 0, sizeof(int)), "clear flag");
     c->device = dev;
@@ -295,6 +313,7 @@ static int check_params(const snap_params *p)
     if (!std::isfinite(p->wself)) return fail(SNAP_EINVAL, "wself must be finite");
     if (p->dedr_dirs != 0 && p->dedr_dirs != 1 && p->dedr_dirs != 3)
         return fail(SNAP_EINVAL, "dedr_dirs must be 0, 1 or 3");
+    if (p->y_kernel < 0 || p->y_kernel > 2) return fail(SNAP_EINVAL, "y_kernel must be 0, 1 or 2");
     return SNAP_OK;
 }
 
@@ -366,6 +385,7 @@ int snap_setup(int twojmax, double rcut, double rfac0, double rmin0, int switch_
     p.switch_flag = switch_flag;
     p.wself = 1.0;
     p.dedr_dirs = 0;
+    p.y_kernel = 0;
     return snap_setup_ex(&p, out);
 }
 

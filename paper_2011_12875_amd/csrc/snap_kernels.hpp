@@ -33,7 +33,19 @@ struct DevTables {
     double *ycp = nullptr, *ycq = nullptr, *nfull = nullptr;
     double *onehot = nullptr;  // identity [nb][nb]: unit coefficient vectors
     int nyrows = 0;
+    // LDS-staged compute_Y (used when y_lds is set and 2J is in range)
+    YLContrib *ylcontrib = nullptr;
+    double *ylcp = nullptr;
+    YLTask *yltask = nullptr;
+    YLGroup *ylgroup = nullptr;
+    int yl_task_off[kYLdsGroupings] = {-1, -1, -1, -1};
+    int yl_group_off[kYLdsGroupings] = {-1, -1, -1, -1};
+    long yl_cost_total = 0;
+    bool y_lds = false;           // the tables are on the device
+    bool y_lds_selected = false;  // and the LDS kernel is the one to run
 };
+// smallest 2J for which the LDS-staged compute_Y is built
+constexpr int kYLdsMinTJ = 2;
 
 // Per-call device workspace.  Per-atom arrays are element-major:
 // X[e * npad + atom], npad = n rounded up to 64.  U holds full matrices

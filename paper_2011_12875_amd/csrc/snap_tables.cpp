@@ -44,6 +44,209 @@ double clebsch_gordan(int J1, int M1, int J2, int M2, int J, int M)
 }
 
 // ---------------------------------------------------------------------------
+// The LDS-staged compute_Y program (see YLContrib, YLTask, YLGroup)
+// ---------------------------------------------------------------------------
+// (q, q1) pairs the kernel's row product evaluates for offset d: q < nq and
+// q1, q2 = q - q1 + d inside 0..2J_max (the compile-time loops).
+static int row_product_pairs(int tj, int d, int nq)
+{
+    int k = 0;
+    for (int q = 0; q < nq; ++q)
+        for (int q1 = 0; q1 <= tj; ++q1) {
+            const int q2 = q - q1 + d;
+            if (q2 >= 0 && q2 <= tj) ++k;
+        }
+    return k;
+}
+
+template <class CG>
+static void build_lds_program(Tables &t, CG cg)
+{
+    const int tj = t.twojmax;
+    const int nunits = (int)t.yrows.size();
+    // the Clebsch-Gordan column table of (J1, J2, J), shared with YContrib
+    std::vector<int> cq_at((tj + 1) * (tj + 1) * (tj + 1), -1);
+    for (const YRowC &r : t.yrows)
+        for (int c = r.cb[0]; c < r.cb[kYWaves]; ++c) {
+            const YContrib &yc = t.ycontrib[c];
+            cq_at[(yc.j1 * (tj + 1) + yc.j2) * (tj + 1) + r.J] = yc.cq_off;
+        }
+    std::vector<std::vector<YLContrib>> ucs(nunits);
+    std::vector<std::vector<long>> ucost(nunits);
+    t.yl_cost.assign(nunits, 0);
+    for (int u = 0; u < nunits; ++u) {
+        const YRowC &r = t.yrows[u];
+        const int J = r.J, p = r.p, two = r.two, nq = r.nq;
+        for (int a = 0; a <= tj; ++a)
+            for (int b = 0; b <= a; ++b) {
+                if (J < a - b || J > a + b || (a + b + J) % 2) continue;
+                YLContrib c{};
+                c.j1 = a;
+                c.j2 = b;
+                c.d = (a + b - J) / 2;
+                int s3[3] = {a, b, J};
+                std::sort(s3, s3 + 3);
+                c.l = -1;
+                for (int l = 0; l < t.nb; ++l)
+                    if (t.comps[l][0] == s3[1] && t.comps[l][1] == s3[0] && t.comps[l][2] == s3[2])
+                        c.l = l;
+                c.factor = (double)((a == J) + (b == J) + 1) * (double)(s3[2] + 1) / (double)(J + 1);
+                // rows of half h: p1 in [p + h + d - b, p + h + d] within [0, a]
+                int lo[2], hi[2];
+                bool any = false;
+                for (int h = 0; h < 2; ++h) {
+                    lo[h] = std::max(0, p + h + c.d - b);
+                    hi[h] = std::min(a, p + h + c.d);
+                    if (h > two) hi[h] = lo[h] - 1;
+                    any = any || lo[h] <= hi[h];
+                }
+                if (!any) continue;
+                c.nsteps = std::max(hi[0] - lo[0] + 1, hi[1] - lo[1] + 1);
+                for (int h = 0; h < 2; ++h) c.lo[h] = lo[h] <= hi[h] ? lo[h] : lo[1 - h];
+                c.cp_off = (int)t.ylcp.size();
+                for (int k = 0; k < c.nsteps; ++k)
+                    for (int h = 0; h < 2; ++h) {
+                        const int p1 = c.lo[h] + k;
+                        const bool ok = lo[h] <= hi[h] && p1 <= hi[h];
+                        t.ylcp.push_back(ok ? cg(a, 2 * p1 - a, b, 2 * (p + h) - J - (2 * p1 - a), J)
+                                            : 0.0);
+                    }
+                c.cq_off = cq_at[(a * (tj + 1) + b) * (tj + 1) + J];
+                const long cost =
+                    (long)c.nsteps * (6 * row_product_pairs(tj, c.d, nq) + 4 * nq + a + b + 6) + 20;
+                ucs[u].push_back(c);
+                ucost[u].push_back(cost);
+                t.yl_cost[u] += cost;
+            }
+    }
+    // contributions stored unit by unit, heaviest first inside a unit
+    std::vector<int> ubase(nunits + 1, 0);
+    for (int u = 0; u < nunits; ++u) {
+        std::vector<int> ord(ucs[u].size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return ucost[u][x] > ucost[u][y]; });
+        std::vector<YLContrib> cs;
+        std::vector<long> cc;
+        for (int k : ord) {
+            cs.push_back(ucs[u][k]);
+            cc.push_back(ucost[u][k]);
+        }
+        ucs[u] = cs;
+        ucost[u] = cc;
+    }
+    for (int gi = 0; gi < kYLdsGroupings; ++gi) {
+        const int G = 1 << gi;
+        t.yl_task_off[gi] = -1;
+        t.yl_group_off[gi] = -1;
+        // units to groups, longest processing time first
+        std::vector<int> uord(nunits);
+        std::iota(uord.begin(), uord.end(), 0);
+        std::stable_sort(uord.begin(), uord.end(),
+                         [&](int x, int y) { return t.yl_cost[x] > t.yl_cost[y]; });
+        std::vector<long> gl(G, 0);
+        std::vector<std::vector<int>> gu(G);
+        for (int u : uord) {
+            const int g = (int)(std::min_element(gl.begin(), gl.end()) - gl.begin());
+            gu[g].push_back(u);
+            gl[g] += t.yl_cost[u];
+        }
+        bool fits = true;
+        for (int g = 0; g < G; ++g) fits = fits && (int)gu[g].size() <= kYLdsWaves;
+        if (!fits) continue;  // every unit needs a wavefront of its own
+        const int task0 = (int)t.yltask.size(), group0 = (int)t.ylgroup.size();
+        t.yl_task_off[gi] = task0;
+        t.yl_group_off[gi] = group0;
+        for (int g = 0; g < G; ++g) {
+            const std::vector<int> &us = gu[g];
+            const int nu = (int)us.size();
+            // wavefronts per unit, in proportion to its cost (at least one)
+            std::vector<int> k(nu, 1);
+            for (int extra = kYLdsWaves - nu; extra > 0 && nu > 0; --extra) {
+                int best = 0;
+                double bv = -1.0;
+                for (int i = 0; i < nu; ++i) {
+                    const double v = (double)t.yl_cost[us[i]] / k[i];
+                    if (v > bv) {
+                        bv = v;
+                        best = i;
+                    }
+                }
+                ++k[best];
+            }
+            // split each unit's contributions over its wavefronts (LPT)
+            struct TaskB { int unit; std::vector<int> cs; long load; };
+            std::vector<TaskB> tasks;
+            std::vector<int> tslot;  // unit slot of each task
+            for (int i = 0; i < nu; ++i) {
+                const int u = us[i];
+                std::vector<TaskB> tt(k[i]);
+                for (auto &x : tt) {
+                    x.unit = u;
+                    x.load = 0;
+                }
+                for (int c = 0; c < (int)ucs[u].size(); ++c) {
+                    auto it = std::min_element(tt.begin(), tt.end(), [](const TaskB &x, const TaskB &y) {
+                        return x.load < y.load;
+                    });
+                    it->cs.push_back(c);
+                    it->load += ucost[u][c];
+                }
+                for (auto &x : tt) {
+                    tasks.push_back(x);
+                    tslot.push_back(i);
+                }
+            }
+            while ((int)tasks.size() < kYLdsWaves) {
+                tasks.push_back(TaskB{-1, {}, 0});
+                tslot.push_back(-1);
+            }
+            // wavefront w runs on SIMD w % 4: balance the SIMDs' sums (LPT)
+            std::vector<int> tord(kYLdsWaves);
+            std::iota(tord.begin(), tord.end(), 0);
+            std::stable_sort(tord.begin(), tord.end(),
+                             [&](int x, int y) { return tasks[x].load > tasks[y].load; });
+            long simd[4] = {0, 0, 0, 0};
+            int fill[4] = {0, 0, 0, 0};
+            std::vector<int> wave_of(kYLdsWaves, -1);
+            for (int x : tord) {
+                int sbest = -1;
+                for (int q = 0; q < 4; ++q)
+                    if (fill[q] < kYLdsWaves / 4 && (sbest < 0 || simd[q] < simd[sbest])) sbest = q;
+                wave_of[x] = 4 * fill[sbest] + sbest;
+                ++fill[sbest];
+                simd[sbest] += tasks[x].load;
+            }
+            std::vector<YLTask> wt(kYLdsWaves);
+            for (int x = 0; x < kYLdsWaves; ++x) {
+                YLTask yt{};
+                yt.unit = tasks[x].unit;
+                const int u = tasks[x].unit;
+                yt.cb = yt.ce = 0;
+                if (u >= 0) {
+                    // this task's contributions, stored contiguously
+                    yt.cb = (int)t.ylcontrib.size();
+                    for (int c : tasks[x].cs) t.ylcontrib.push_back(ucs[u][c]);
+                    yt.ce = (int)t.ylcontrib.size();
+                }
+                wt[wave_of[x]] = yt;
+            }
+            t.yltask.insert(t.yltask.end(), wt.begin(), wt.end());
+            YLGroup gr{};
+            gr.nunits = nu;
+            int nt = 0;
+            for (int i = 0; i < nu; ++i) {
+                gr.unit[i] = us[i];
+                gr.tb[i] = nt;
+                for (int x = 0; x < kYLdsWaves; ++x)
+                    if (tslot[x] == i) gr.tw[nt++] = wave_of[x];
+            }
+            gr.tb[nu] = nt;
+            t.ylgroup.push_back(gr);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Tables
 // ---------------------------------------------------------------------------
 void build_tables(int tj, Tables &t)
@@ -226,6 +429,8 @@ void build_tables(int tj, Tables &t)
             t.yrows.push_back(pr.row);
         }
     }
+
+    if (tj <= kYLdsMaxTJ) build_lds_program(t, cg);
 
     // bispectrum program (eq. (z)): for each canonical (J1, J2, J) and each
     // stored (p, q) of rank J, the Clebsch-Gordan terms of Z(p, q)

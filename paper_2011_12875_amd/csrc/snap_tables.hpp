@@ -87,6 +87,44 @@ struct YRowC {
     double einv[2][8];        // 1/N of the outputs: Re(Y~ conj(U)) / N = w Re(Y conj(U))
 };
 
+// LDS-staged compute_Y (2J <= kYLdsMaxTJ).  A workgroup holds the full U of
+// kYLdsAtoms atoms in LDS and computes a group of units (row pairs p, p + 1
+// of one J) for them with kYLdsWaves wavefronts; lanes 0..31 take row p and
+// lanes 32..63 row p + 1 of the same 32 atoms.  A unit's contributions are
+// split into tasks, one per wavefront, whose partial sums are reduced in LDS.
+constexpr int kYLdsAtoms = 32;
+constexpr int kYLdsWaves = 16;
+constexpr int kYLdsMaxTJ = 8;
+constexpr int kYLdsGroupings = 4;  // programs for 1, 2, 4 and 8 groups of units
+// One contribution (J1 >= J2 -> J) of a unit in the LDS kernel.  Step k of its
+// loop pairs U^J1 row lo[h] + k with U^J2 row p + h - (lo[h] + k) + d for the
+// half h of the wavefront (row p + h of Y): the half of row p + 1 walks its
+// own range, shifted by one, so both halves run max(rows) steps instead of
+// the union of their ranges.  cp[cp_off + 2k + h] is the row coefficient of
+// half h at step k (zero where that half has no valid row).
+struct YLContrib {
+    int32_t j1, j2, d, l;
+    double factor;    // multiplicity * (J_max + 1)/(J + 1)
+    int32_t lo[2];    // first U^J1 row of each half
+    int32_t nsteps;
+    int32_t cp_off;
+    int32_t cq_off;   // as YContrib
+    int32_t pad;
+};
+// One wavefront's task: contributions cb .. ce-1 of unit `unit` (an index
+// into yrows; -1 for an idle wavefront).
+struct YLTask {
+    int32_t unit, cb, ce, pad;
+};
+// The units of one group and the wavefronts (tasks) of each: slot s of group
+// g is reduced by wavefront s, summing the partials of tasks tb[s] .. tb[s+1]-1.
+struct YLGroup {
+    int32_t nunits;
+    int32_t unit[kYLdsWaves];
+    int32_t tb[kYLdsWaves + 1];  // slot s: waves tw[tb[s]] .. tw[tb[s+1]-1]
+    int32_t tw[kYLdsWaves];
+};
+
 struct Tables {
     int twojmax = 0;
     int nhalf = 0;
@@ -107,6 +145,16 @@ struct Tables {
     std::vector<YContrib> ycontrib;
     std::vector<YRowC> yrows;               // sorted by decreasing cost
     std::vector<double> ycp, ycq;           // Clebsch-Gordan coefficient tables
+    // LDS-staged compute_Y: contributions and cp table, and for each grouping
+    // gi (G = 1 << gi groups) the tasks [G][kYLdsWaves] and groups [G],
+    // stored one grouping after another (offsets yl_task_off, yl_group_off)
+    std::vector<YLContrib> ylcontrib;
+    std::vector<double> ylcp;
+    std::vector<YLTask> yltask;
+    std::vector<YLGroup> ylgroup;
+    int yl_task_off[kYLdsGroupings] = {0, 0, 0, 0};
+    int yl_group_off[kYLdsGroupings] = {0, 0, 0, 0};
+    std::vector<long> yl_cost;              // estimated cost per unit (index as yrows)
     long yterms = 0;                         // Clebsch-Gordan products per atom
     long ypartials = 0;                      // (contribution, p1, q) partial sums per atom
     std::vector<double> nfull;              // N of every full element, blocks of (J+1)^2

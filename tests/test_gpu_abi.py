@@ -22,7 +22,7 @@ def _setup(ncell, seed, tj=4):
 
 
 def test_backward_with_other_pair_count_is_rejected():
-    torch, snapmi, pot, nl, pos, box, tpos, tbeta = _setup(3, 60)
+    torch, snapmi, pot, nl, pos, box, tpos, tbeta = _setup(4, 60)   # 12.7 A >= 2 x 5.5 A
     pot.forward(tpos, box, nl, tbeta)
     wider = snapmi.NeighborList.build(pos, box, 5.5)  # a skin: more pairs, same atoms
     assert wider.npairs > nl.npairs
