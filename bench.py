@@ -52,6 +52,24 @@ def _element_costs(twojmax):
     return nel, u, du
 
 
+def _generator_costs(twojmax):
+    """Per-pair flops of compute_dE in the generator form: for every stored
+    element of every level, Y~ conj(u) against its own column (8 flops, with
+    S0), the column before (8, from column 1 on) and the column after (8,
+    while that column is stored), and the mirror term of the last stored
+    column (8, on column ceil(J/2) - 1); 4 per weighted column sum; then
+    per direction the derivatives of the Cayley-Klein pair and the three
+    complex dot products (about 60 flops)."""
+    f = 0
+    for J in range(1, twojmax + 1):
+        for c in range(J // 2 + 1):
+            has_m, has_p = c >= 1, 2 * (c + 1) <= J
+            mir = (J % 2 == 0 and 2 * c + 2 == J) or (J % 2 == 1 and 2 * c + 1 == J)
+            nterm = 1 + has_m + has_p + mir
+            f += (J + 1) * 8 * nterm + 4 * nterm + 1
+    return f + 3 * 60
+
+
 def algorithmic_flops(twojmax, natoms, npairs, nterms, npartials):
     nel, u_rec, du_rec = _element_costs(twojmax)
     flops = {
@@ -60,9 +78,11 @@ def algorithmic_flops(twojmax, natoms, npairs, nterms, npartials):
         # 10 per Clebsch-Gordan product (complex product, real weight,
         # accumulate) and 4 per partial sum (row coefficient times the sum)
         "compute_Y": natoms * (10 * nterms + 4 * npartials),
-        # u once, du for three directions, four dot products with Y, and
-        # dE = f_c' n S0 + f_c S per direction
-        "compute_dE": npairs * (u_rec + 3 * du_rec + 16 * nel + 9),
+        # the generator form: u once (the recursion) and the sums against
+        # Y~ that give all three directions (the tangent form, u plus a
+        # derivative recursion per direction, would count
+        # u_rec + 3 du_rec + 16 nel + 9 per pair)
+        "compute_dE": npairs * (u_rec + _generator_costs(twojmax)),
         # 6 per pair (gather) and 4 per element (energy)
         "update_forces": 6 * npairs + 4 * nel * natoms,
     }
@@ -332,6 +352,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="bcc2000_2j8", choices=sorted(METRIC_LABEL))
     ap.add_argument("--dedr-dirs", type=int, default=0)
+    ap.add_argument("--u-kernel", type=int, default=0,
+                    help="compute_U variant: 0 auto, 1 column workgroups, 2 one pair per lane")
+    ap.add_argument("--dedr-kernel", type=int, default=0,
+                    help="compute_dE variant: 0 auto, 1 tangent form, 2 generator form (Y~ in "
+                         "LDS), 3 generator form (Y~ through the texture path), 4 generator "
+                         "form with one wavefront per block")
     ap.add_argument("--y-kernel", type=int, default=0,
                     help="compute_Y variant: 0 auto, 1 rows through the texture path, "
                          "2 LDS-staged")
@@ -371,7 +397,8 @@ def main():
         pos, box, beta, tj = wl.make(args.workload[:-5] if quadratic else args.workload)
     n = len(pos)
     pot = snapmi.SnapPotential(tj, wl.RCUT, wl.RFAC0, wl.RMIN0, 1, dedr_dirs=args.dedr_dirs,
-                               y_kernel=args.y_kernel)
+                               y_kernel=args.y_kernel, dedr_kernel=args.dedr_kernel,
+                               u_kernel=args.u_kernel)
     nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
     tpos = torch.as_tensor(pos, device="cuda")
     tbeta = torch.as_tensor(beta, device="cuda")
@@ -458,7 +485,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "atoms": n, "pairs": nl.npairs, "twojmax": tj,
-                   "y_kernel": args.y_kernel, "dedr_dirs": args.dedr_dirs,
+                   "u_kernel": args.u_kernel, "y_kernel": args.y_kernel,
+                   "dedr_kernel": args.dedr_kernel,
+                   "dedr_dirs": args.dedr_dirs,
                    "ncoeff": pot.ncoeff, "rcut": wl.RCUT, "rfac0": wl.RFAC0,
                    "lattice": "bcc a=3.1803 A", "parallelism": "single GPU"},
         "timing": timing,

@@ -71,6 +71,17 @@ typedef struct {
     int y_kernel;      /* compute_Y variant: 0 auto (the measured faster: rows
                         * through the texture path), 1 rows through the texture
                         * path, 2 U staged in LDS (2 <= 2J <= 8, else as 1)  */
+    int dedr_kernel;   /* compute_dE variant: 0 auto (2), 1 tangent form
+                        * (one derivative recursion per direction, dedr_dirs
+                        * directions per lane), 2 generator form (one walk
+                        * of the recursion per pair, three sums independent of
+                        * the direction) with Y~ staged in LDS and, from
+                        * 2J = 5, the columns split over two wavefronts, 3 as
+                        * 2 with Y~ read through the texture path, 4 as 2 with
+                        * one wavefront per block of pairs                   */
+    int u_kernel;      /* compute_U variant: 0 auto (1), 1 one workgroup per
+                        * column of the stored half (two pairs per lane, seed
+                        * paths), 2 one pair per lane walking every column   */
 } snap_params;
 
 /* Create a context for one parameter set.  Builds the host index tables

@@ -23,6 +23,7 @@ UNITS = [
     ("snap_y.hip", [], "snap_y.o"),
     ("snap_dedr.hip", ["-DSNAP_DEDR_LOW"], "snap_dedr_low.o"),
     ("snap_dedr.hip", [], "snap_dedr_high.o"),
+    ("snap_dedr_gen.hip", [], "snap_dedr_gen.o"),
     ("snap_misc.hip", [], "snap_misc.o"),
     ("snap_mlp.hip", [], "snap_mlp.o"),
 ]

@@ -197,6 +197,7 @@ static int ensure_device(snap_ctx *c)
         HIP_TRY(upload(d.onehot, eye), "upload unit coefficient vectors");
     }
     d.nyrows = (int)t.yrows.size();
+    d.nhalf = t.nhalf;
     if (!t.ylcontrib.empty() && c->prm.y_kernel != 1) {
         HIP_TRY(upload(d.ylcontrib, t.ylcontrib), "upload ylcontrib");
         HIP_TRY(upload(d.ylcp, t.ylcp), "upload ylcp");
@@ -314,6 +315,9 @@ static int check_params(const snap_params *p)
     if (p->dedr_dirs != 0 && p->dedr_dirs != 1 && p->dedr_dirs != 3)
         return fail(SNAP_EINVAL, "dedr_dirs must be 0, 1 or 3");
     if (p->y_kernel < 0 || p->y_kernel > 2) return fail(SNAP_EINVAL, "y_kernel must be 0, 1 or 2");
+    if (p->dedr_kernel < 0 || p->dedr_kernel > 4)
+        return fail(SNAP_EINVAL, "dedr_kernel must be 0 .. 4");
+    if (p->u_kernel < 0 || p->u_kernel > 2) return fail(SNAP_EINVAL, "u_kernel must be 0, 1 or 2");
     return SNAP_OK;
 }
 
@@ -351,6 +355,20 @@ static int dedr_dirs(const snap_ctx *c)
     return c->prm.twojmax <= 6 ? 3 : 1;
 }
 
+// compute_dE: the generator form (one walk of the recursion per pair, three
+// direction-independent sums) unless the tangent form is asked for.
+static hipError_t run_dedr(const snap_ctx *c, int n, int npairs, int, const double *pos,
+                           const int *off, const int *nbr, const int *pair_atom,
+                           const double2 *Y, const Geom &g, double *dE, hipStream_t s)
+{
+    const int k = c->prm.dedr_kernel ? c->prm.dedr_kernel : 2;
+    if (k == 1)
+        return launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, c->tab.nhalf, pos, nbr,
+                           pair_atom, Y, c->dev, g, dE, s);
+    return launch_dedr_gen(c->prm.twojmax, k - 2, npairs, c->tab.nhalf, pos, nbr, pair_atom, Y,
+                           g, dE, s);
+}
+
 extern "C" {
 
 const char *snap_last_error(void) { return g_err.c_str(); }
@@ -386,6 +404,8 @@ int snap_setup(int twojmax, double rcut, double rfac0, double rmin0, int switch_
     p.wself = 1.0;
     p.dedr_dirs = 0;
     p.y_kernel = 0;
+    p.dedr_kernel = 0;
+    p.u_kernel = 0;
     return snap_setup_ex(&p, out);
 }
 
@@ -514,7 +534,8 @@ static int run_u(snap_ctx *c, int n, int npairs, const double *pos, const Geom &
                  const int *nbr, hipStream_t s)
 {
     (void)npairs;
-    HIP_TRY(launch_compute_u(c->prm.twojmax, n, c->work.npad, pos, off, nbr, c->dev, g, c->work.U,
+    HIP_TRY(launch_compute_u(c->prm.twojmax, c->prm.u_kernel ? c->prm.u_kernel : 1, n,
+                             c->work.npad, pos, off, nbr, c->dev, g, c->work.U,
                              c->work.pair_atom, c->work.flag, s),
             "compute_U launch");
     return SNAP_OK;
@@ -575,8 +596,7 @@ static int compute_impl(snap_ctx *c, int n, int npairs, const double *pos, const
     }
     if (npairs > 0) {
         StageTimer tm(c, 2, s);
-        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
-                            w.Y, c->dev, g, dE, s),
+        HIP_TRY(run_dedr(c, n, npairs, w.npad, pos, off, nbr, w.pair_atom, w.Y, g, dE, s),
                 "compute_dE launch");
         tm.finish();
     }
@@ -648,8 +668,7 @@ int snap_compute_quadratic(snap_ctx *c, int n, int npairs, const double *pos,
     }
     if (npairs > 0) {
         StageTimer tm(c, 2, s);
-        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
-                            w.Y, c->dev, g, dE, s),
+        HIP_TRY(run_dedr(c, n, npairs, w.npad, pos, off, nbr, w.pair_atom, w.Y, g, dE, s),
                 "compute_dE launch");
         tm.finish();
     }
@@ -749,8 +768,7 @@ int snap_backward(snap_ctx *c, int n, int npairs, const double *pos, const doubl
                              c->tab.nb, nullptr, 0, grad_energy, nullptr, s),
             "compute_Y launch");
     if (npairs > 0)
-        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom, w.Y,
-                            c->dev, g, dE, s),
+        HIP_TRY(run_dedr(c, n, npairs, w.npad, pos, off, nbr, w.pair_atom, w.Y, g, dE, s),
                 "compute_dE launch");
     HIP_TRY(launch_gather(n, w.npad, c->dev.nyrows, off, rev, dE, nullptr, nullptr, force, s),
             "update_forces launch");
@@ -768,7 +786,8 @@ int snap_copy_workspace(snap_ctx *c, int which, int n, double *dst, void *stream
     const double2 *src = which == 0 ? c->work.U : c->work.Y;
     const int *map = which == 0 ? c->dev.half2full : nullptr;
     const double *scale = which == 0 ? nullptr : c->dev.unscale_y;
-    HIP_TRY(launch_unscale(c->last_n, c->work.npad, c->tab.nhalf, src, map, scale, dst,
+    const int se = which == 0 ? c->work.npad : 1, sa = which == 0 ? 1 : c->tab.nhalf;
+    HIP_TRY(launch_unscale(c->last_n, se, sa, c->tab.nhalf, src, map, scale, dst,
                            (hipStream_t)stream),
             "copy workspace");
     return SNAP_OK;
@@ -885,8 +904,7 @@ int snap_jacobian(snap_ctx *c, int n, int npairs, const double *pos, const doubl
         HIP_TRY(launch_compute_y(c->prm.twojmax, n, w.npad, w.U, w.Y, c->dev, el, 0, nb, nullptr, 0,
                                  nullptr, nullptr, s),
                 "compute_Y launch");
-        HIP_TRY(launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, w.npad, pos, nbr, w.pair_atom,
-                            w.Y, c->dev, g, w.dE, s),
+        HIP_TRY(run_dedr(c, n, npairs, w.npad, pos, off, nbr, w.pair_atom, w.Y, g, w.dE, s),
                 "compute_dE launch");
         HIP_TRY(launch_pack_jac(npairs, nb, l, w.dE, jac, s), "Jacobian store");
     }

@@ -19,14 +19,15 @@ struct DedrState {
     double S0, S[ND];
 };
 
-// Y~ rows eb .. eb + J of the atom (the level's stored elements) into y.
+// Y~ elements eb .. eb + J of the atom (the level's stored elements) into y;
+// Y points at the atom's row of Y~ (atom-major).
 template <int TJ>
 __device__ __forceinline__ void load_level(double2 (&y)[TJ + 1], int J, int eb,
                                            const double2 *__restrict__ Y, unsigned i, int npad)
 {
 #pragma unroll
     for (int p = 0; p <= TJ; ++p)
-        if (p <= J) y[p] = load_row(Y, (size_t)(eb + p), npad, i * 16u);
+        if (p <= J) y[p] = Y[eb + p];
 }
 
 // One level: recursion for poly and its derivatives, then the dot with Y~.
@@ -106,7 +107,7 @@ __device__ __forceinline__ void dedr_level(int J, int Jn, int ebn, DedrState<TJ,
             if constexpr (kDedrStraight<TJ>)
                 y = st.y[p];
             else
-                y = load_row(Y, (size_t)(eb + p), npad, i * 16u);
+                y = Y[eb + p];
             st.S0 += y.x * st.col[p].x + y.y * st.col[p].y;
 #pragma unroll
             for (int d = 0; d < ND; ++d) st.S[d] += y.x * st.dcol[d][p].x + y.y * st.dcol[d][p].y;
@@ -202,7 +203,7 @@ struct DedrColumns<TJ, ND, TJ / 2 + 1> {
 };
 
 template <int TJ, int ND>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_dedr(int npairs, int npad, const double *__restrict__ pos,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_dedr(int npairs, int nh, const double *__restrict__ pos,
                                              const int *__restrict__ nbr,
                                              const int *__restrict__ pair_atom,
                                              const double2 *__restrict__ Y, Geom g,
@@ -226,7 +227,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     const int tt = valid ? t : npairs - 1;
     const int i = pair_atom[tt];
     // Y~ of J = 0 and of the first level of column 0, ahead of the geometry
-    const double y00 = load_row(Y, 0, npad, (unsigned)i * 16u).x;
+    const double2 *__restrict__ Yi = Y + (size_t)i * nh;  // the atom's row of Y~
+    const int npad = 0;  // unused by the atom-major loads
+    const double y00 = Yi[0].x;
     double rv[3];
     const int k = nbr[tt];
     min_image(pos, i, k, g, rv);
@@ -264,9 +267,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
         for (int d = 0; d < ND; ++d) st.dseed[d][p] = make_double2(0.0, 0.0);
     }
     if constexpr (TJ >= 1 && kDedrStraight<TJ>)
-        load_level<TJ>(st.y, 1, hbase_of(1), Y, (unsigned)i, npad);
+        load_level<TJ>(st.y, 1, hbase_of(1), Yi, (unsigned)i, npad);
     st.S0 = y00;  // J = 0: poly = 1, dpoly = 0
-    DedrColumns<TJ, ND, 0>::run(st, pg.a, pg.b, da, db, Y, (unsigned)i, npad);
+    DedrColumns<TJ, ND, 0>::run(st, pg.a, pg.b, da, db, Yi, (unsigned)i, npad);
     if (valid) {
 #pragma unroll
         for (int d = 0; d < ND; ++d)

@@ -33,6 +33,7 @@ struct DevTables {
     double *ycp = nullptr, *ycq = nullptr, *nfull = nullptr;
     double *onehot = nullptr;  // identity [nb][nb]: unit coefficient vectors
     int nyrows = 0;
+    int nhalf = 0;  // stored-half elements per atom (the row length of Y~)
     // LDS-staged compute_Y (used when y_lds is set and 2J is in range)
     YLContrib *ylcontrib = nullptr;
     double *ylcp = nullptr;
@@ -47,9 +48,11 @@ struct DevTables {
 // smallest 2J for which the LDS-staged compute_Y is built
 constexpr int kYLdsMinTJ = 2;
 
-// Per-call device workspace.  Per-atom arrays are element-major:
-// X[e * npad + atom], npad = n rounded up to 64.  U holds full matrices
-// (sum (J+1)^2 elements), Y the scaled stored half.
+// Per-call device workspace.  U is element-major, U[e * npad + atom] (npad =
+// n rounded up to 64), full matrices (sum (J+1)^2 elements): compute_Y reads
+// one element of 64 consecutive atoms per load.  Y holds the scaled stored
+// half atom-major, Y[atom * nhalf + e]: compute_dE reads the elements of one
+// atom (a lane's, or a wavefront's) at immediate offsets from one base.
 struct Work {
     double2 *U = nullptr, *Y = nullptr;
     double *dE = nullptr;
@@ -59,9 +62,10 @@ struct Work {
     int npad = 0;
 };
 
-hipError_t launch_compute_u(int twojmax, int n, int npad, const double *pos, const int *off,
-                            const int *nbr, const DevTables &T, const Geom &g, double2 *U,
-                            int *pair_atom, int *flag, hipStream_t s);
+// variant 1: one workgroup per column of the stored half; 2: one pair per lane
+hipError_t launch_compute_u(int twojmax, int variant, int n, int npad, const double *pos,
+                            const int *off, const int *nbr, const DevTables &T, const Geom &g,
+                            double2 *U, int *pair_atom, int *flag, hipStream_t s);
 
 // coefficients: beta[nb] shared, beta[n][nb] per atom (per_atom_beta), or
 // beta[nelem][nb] per element of btype[n] (btype not NULL)
@@ -76,7 +80,8 @@ hipError_t launch_bispectrum(int n, int npad, const double2 *U, const DevTables 
                              double *B, const double *beta, int per_atom_beta, double *energy,
                              hipStream_t s, int nfull);
 
-hipError_t launch_dedr_low(int twojmax, int dirs, int npairs, int npad, const double *pos,
+// tangent form (snap_dedr.hip); nh = row length of the atom-major Y~
+hipError_t launch_dedr_low(int twojmax, int dirs, int npairs, int nh, const double *pos,
                            const int *nbr, const int *pair_atom, const double2 *Y,
                            const DevTables &T, const Geom &g, double *dE, hipStream_t s);
 hipError_t launch_dedr_high(int twojmax, int dirs, int npairs, int npad, const double *pos,
@@ -90,6 +95,13 @@ inline hipError_t launch_dedr(int twojmax, int dirs, int npairs, int npad, const
                ? launch_dedr_low(twojmax, dirs, npairs, npad, pos, nbr, pair_atom, Y, T, g, dE, s)
                : launch_dedr_high(twojmax, dirs, npairs, npad, pos, nbr, pair_atom, Y, T, g, dE, s);
 }
+
+// compute_dE in the generator form (snap_dedr_gen.hip): mapping 0 with the
+// block's rows of Y~ staged in LDS, 1 read through the texture path, 2 staged
+// with one wavefront per block; nh = row length of the atom-major Y~
+hipError_t launch_dedr_gen(int twojmax, int mapping, int npairs, int nh, const double *pos,
+                           const int *nbr, const int *pair_atom, const double2 *Y, const Geom &g,
+                           double *dE, hipStream_t s);
 
 hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *rev,
                          const double *dE, const double *Epart, double *energy, double *force,
@@ -112,8 +124,9 @@ int beta_grad_blocks(int n);
 hipError_t launch_beta_grad(int n, int nb, const double *g, const double *B, int per_atom,
                             double *part, double *out, hipStream_t s);
 
-// dst[e][atom][re/im] = scale[e] * src[map[e] * npad + atom] for atom < n
-hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const int *map,
+// dst[e][atom][re/im] = scale[e] * src[map[e] * se + atom * sa] for atom < n
+// (element-major: se = npad, sa = 1; atom-major: se = 1, sa = row length)
+hipError_t launch_unscale(int n, int se, int sa, int nhalf, const double2 *src, const int *map,
                           const double *scale, double *dst, hipStream_t s);
 
 // ---------------------------------------------------------------------------

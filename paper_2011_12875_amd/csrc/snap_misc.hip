@@ -278,7 +278,7 @@ __global__ void k_beta_grad_atom(long long total, int nb, const double *__restri
 }
 
 // dst[e][i] = scale[e] * src[map[e] * npad + i] (map, scale optional)
-__global__ void k_unscale(int n, int npad, int nhalf, const double2 *__restrict__ src,
+__global__ void k_unscale(int n, int se, int sa, int nhalf, const double2 *__restrict__ src,
                           const int *__restrict__ map, const double *__restrict__ scale,
                           double *__restrict__ dst)
 {
@@ -287,7 +287,7 @@ __global__ void k_unscale(int n, int npad, int nhalf, const double2 *__restrict_
     const int e = (int)(k / n), i = (int)(k - (size_t)e * n);
     const int row = map ? map[e] : e;
     const double sc = scale ? scale[e] : 1.0;
-    const double2 v = src[(size_t)row * npad + i];
+    const double2 v = src[(size_t)row * se + (size_t)i * sa];
     dst[2 * k + 0] = sc * v.x;
     dst[2 * k + 1] = sc * v.y;
 }
@@ -386,12 +386,12 @@ hipError_t launch_beta_grad(int n, int nb, const double *g, const double *B, int
     return hipGetLastError();
 }
 
-hipError_t launch_unscale(int n, int npad, int nhalf, const double2 *src, const int *map,
+hipError_t launch_unscale(int n, int se, int sa, int nhalf, const double2 *src, const int *map,
                           const double *scale, double *dst, hipStream_t s)
 {
     const size_t tot = (size_t)n * nhalf;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_unscale, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, npad,
+    hipLaunchKernelGGL(k_unscale, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, se, sa,
                        nhalf, src, map, scale, dst);
     return hipGetLastError();
 }

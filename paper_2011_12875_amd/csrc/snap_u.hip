@@ -334,11 +334,158 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void
     }
 }
 
-template <int TJ>
-hipError_t launch_u_t(int n, int npad, const double *pos, const int *off, const int *nbr,
-                      const Geom &g, const UInfo *uinfo, double2 *U, int *pair_atom, int *flag,
-                      hipStream_t s)
+// ---------------------------------------------------------------------------
+// compute_U, one pair per lane
+//
+// A workgroup is one wavefront holding two atoms of 32 lanes each; every lane
+// walks one pair (neighbour 32c + slot of chunk c) through every column of
+// the stored half in turn -- column 0 from f_c, column q + 1 from the mirror
+// of column q at level 2q + 1 -- so the pair geometry is computed once and
+// no level is computed twice.  The values are staged in LDS 32 elements at a
+// time; at each flush every lane sums one (atom, element) over its atom's 32
+// lanes in a fixed order and writes it, with its mirror, as a full matrix of
+// true values.
+// ---------------------------------------------------------------------------
+constexpr int kU2Lanes = 32;  // lanes per atom
+constexpr int kU2Stage = 32;  // staged elements per flush (64 lanes / 2 atoms)
+
+struct U2Stage {
+    double2 v[kU2Stage][65];  // [element slot][lane], rows padded against bank conflicts
+    int code[kU2Stage];       // half index of the slot's element | diagonal flag << 24
+};
+
+__device__ __forceinline__ void u2_flush(U2Stage &st, int nst, int lane, int i0, int n, int npad,
+                                         int chunk, double wself, const UInfo *__restrict__ uinfo,
+                                         double2 *__restrict__ U)
 {
+    __syncthreads();
+    const int h = lane >> 5, s = lane & 31;
+    if (s < nst) {
+        const int code = st.code[s];
+        const UInfo ui = uinfo[code & 0xffffff];
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < kU2Lanes; j0 += 8) {
+            // eight reads in flight at a time (all 32 hoisted would hold 128
+            // registers)
+#pragma unroll
+            for (int j = j0; j < j0 + 8; ++j) {
+                const double2 v = st.v[s][h * kU2Lanes + j];
+                sr += v.x;
+                si += v.y;
+            }
+            memory_fence_compiler();
+        }
+        const int ia = i0 + h;
+        if (ia < n) {
+            const size_t idx = (size_t)ui.fi * npad + ia;
+            double br = 0.0, bi = 0.0;
+            if (chunk == 0) {
+                br = (code >> 24) ? wself : 0.0;
+            } else {
+                const double2 old = U[idx];
+                br = old.x;
+                bi = old.y;
+            }
+            const double2 v = make_double2(br + ui.nrm * sr, bi + ui.nrm * si);
+            U[idx] = v;
+            if (ui.fm >= 0)
+                U[(size_t)ui.fm * npad + ia] = make_double2(ui.msign * v.x, -ui.msign * v.y);
+        }
+    }
+    __syncthreads();
+}
+
+// Stage element (J, p, q) (half index e) of every lane; flush when full.
+__device__ __forceinline__ void u2_emit(U2Stage &st, int &nst, int lane, double2 v, int e,
+                                        bool diag, int i0, int n, int npad, int chunk,
+                                        double wself, const UInfo *__restrict__ uinfo,
+                                        double2 *__restrict__ U)
+{
+    st.v[nst][lane] = v;
+    if (lane == 0) st.code[nst] = e | (diag ? (1 << 24) : 0);
+    if (++nst == kU2Stage) {
+        u2_flush(st, nst, lane, i0, n, npad, chunk, wself, uinfo, U);
+        nst = 0;
+    }
+}
+
+template <int TJ>
+__global__ __launch_bounds__(64) void k_compute_u2(int n, int npad, const double *__restrict__ pos,
+                                                   const int *__restrict__ off,
+                                                   const int *__restrict__ nbr, Geom g,
+                                                   const UInfo *__restrict__ uinfo,
+                                                   double2 *__restrict__ U,
+                                                   int *__restrict__ pair_atom,
+                                                   int *__restrict__ flag)
+{
+    __shared__ U2Stage st;
+    const int lane = threadIdx.x;
+    const int h = lane >> 5, slot = lane & 31;
+    const int i0 = (int)blockIdx.x * 2;
+    const int i = i0 + h;
+    int mx = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int cnt = (i0 + k < n) ? off[i0 + k + 1] - off[i0 + k] : 0;
+        mx = cnt > mx ? cnt : mx;
+    }
+    const int nchunk = mx > 0 ? (mx + kU2Lanes - 1) / kU2Lanes : 1;
+    const int myn = (i < n) ? off[i + 1] - off[i] : 0;
+    const int mybeg = (i < n) ? off[i] : 0;
+    for (int c = 0; c < nchunk; ++c) {
+        const int sn = c * kU2Lanes + slot;
+        PairGeom pg;
+        slot_geometry((i < n) && (sn < myn), i, mybeg + sn, true, pos, nbr, g, pair_atom, flag,
+                      pg);
+        double2 col[TJ + 1], seed[TJ + 1];
+#pragma unroll
+        for (int p = 0; p <= TJ; ++p) seed[p] = make_double2(0.0, 0.0);
+        int nst = 0;
+        // J = 0: f_c
+        u2_emit(st, nst, lane, make_double2(pg.fc, 0.0), 0, true, i0, n, npad, c, g.wself, uinfo,
+                U);
+#pragma unroll
+        for (int q = 0; q <= TJ / 2; ++q) {
+#pragma unroll
+            for (int p = 0; p <= TJ; ++p)
+                col[p] = (q > 0 && p < 2 * q) ? seed[p] : make_double2(0.0, 0.0);
+            if (q == 0) col[0] = make_double2(pg.fc, 0.0);
+#pragma unroll
+            for (int J = (q == 0 ? 1 : 2 * q); J <= TJ; ++J) {
+                poly_step<TJ>(J, col, pg.a, pg.b);
+                if (J == 2 * q + 1 && 2 * q + 2 <= TJ) {
+                    // seed of column q + 1: (-1)^(q+1-p) conj(poly_{2q+1-p, q})
+#pragma unroll
+                    for (int p = 0; p <= TJ; ++p)
+                        if (p <= 2 * q + 1) {
+                            const double sg = ((q + 1 - p) & 1) ? -1.0 : 1.0;
+                            const double2 m = col[2 * q + 1 - p];
+                            seed[p] = make_double2(sg * m.x, -sg * m.y);
+                        }
+                }
+                const int eb = hbase_of(J) + q * (J + 1);
+#pragma unroll
+                for (int p = 0; p <= TJ; ++p)
+                    if (p <= J)
+                        u2_emit(st, nst, lane, col[p], eb + p, p == q, i0, n, npad, c, g.wself,
+                                uinfo, U);
+            }
+        }
+        if (nst > 0) u2_flush(st, nst, lane, i0, n, npad, c, g.wself, uinfo, U);
+    }
+}
+
+template <int TJ>
+hipError_t launch_u_t(int variant, int n, int npad, const double *pos, const int *off,
+                      const int *nbr, const Geom &g, const UInfo *uinfo, double2 *U,
+                      int *pair_atom, int *flag, hipStream_t s)
+{
+    if (variant == 2) {
+        hipLaunchKernelGGL(k_compute_u2<TJ>, dim3((n + 1) / 2), dim3(64), 0, s, n, npad, pos, off,
+                           nbr, g, uinfo, U, pair_atom, flag);
+        return hipGetLastError();
+    }
     const int nblk = ((n + kUAtoms - 1) / kUAtoms) * kUGroups<TJ>;
     hipLaunchKernelGGL(k_compute_u<TJ>, dim3(nblk), dim3(64), 0, s, n, npad, pos, off, nbr, g,
                        uinfo, U, pair_atom, flag);
@@ -352,13 +499,14 @@ hipError_t launch_u_t(int n, int npad, const double *pos, const int *off, const 
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 #endif
 
-hipError_t launch_compute_u(int twojmax, int n, int npad, const double *pos, const int *off,
-                            const int *nbr, const DevTables &T, const Geom &g, double2 *U,
-                            int *pair_atom, int *flag, hipStream_t s)
+hipError_t launch_compute_u(int twojmax, int variant, int n, int npad, const double *pos,
+                            const int *off, const int *nbr, const DevTables &T, const Geom &g,
+                            double2 *U, int *pair_atom, int *flag, hipStream_t s)
 {
     switch (twojmax) {
 #define X(k) \
-    case k: return launch_u_t<k>(n, npad, pos, off, nbr, g, T.uinfo, U, pair_atom, flag, s);
+    case k:  \
+        return launch_u_t<k>(variant, n, npad, pos, off, nbr, g, T.uinfo, U, pair_atom, flag, s);
         SNAP_TJ_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -177,7 +177,7 @@ struct YDispatch<TJ, TJ + 1> {
 constexpr int kYGroup = 4;
 template <int TJ>
 __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2, 4))) void k_compute_y(
-    int n, int npad, int nblk8, const double2 *__restrict__ U, double2 *__restrict__ Y,
+    int n, int npad, int nhalf, int nblk8, const double2 *__restrict__ U, double2 *__restrict__ Y,
     const YRowC *__restrict__ rows, const YContrib *__restrict__ contribs,
     const double *__restrict__ cpt, const double *__restrict__ cqt,
     const double *__restrict__ beta, int per_atom_beta, int nb, const int *__restrict__ btype,
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(64 * kYWaves) __attribute__((amdgpu_waves_per_eu(2,
                 const double sc = row->oscale[r][q];
                 s.x *= sc;
                 s.y *= sc;
-                Y[(size_t)(row->ebase + r + q * (J + 1)) * npad + atom] = s;
+                Y[(size_t)atom * nhalf + row->ebase + r + q * (J + 1)] = s;
                 const double2 u = U[(size_t)(row->frow + r * (J + 1) + q) * npad + atom];
                 e += (s.x * u.x + s.y * u.y) * row->einv[r][q];
             }
@@ -341,7 +341,7 @@ struct YLDispatch<TJ, TJ + 1> {
 // the block's U.
 template <int TJ>
 __global__ __launch_bounds__(64 * kYLdsWaves) void k_compute_y_lds(
-    int n, int npad, int G, const double2 *__restrict__ U, double2 *__restrict__ Y,
+    int n, int npad, int nhalf, int G, const double2 *__restrict__ U, double2 *__restrict__ Y,
     const YRowC *__restrict__ rows, const YLTask *__restrict__ tasks,
     const YLGroup *__restrict__ groups, const YLContrib *__restrict__ contribs,
     const double *__restrict__ cpt, const double *__restrict__ cqt,
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(64 * kYLdsWaves) void k_compute_y_lds(
                 const double sc = row->oscale[h][q];
                 s.x *= sc;
                 s.y *= sc;
-                Y[(size_t)(row->ebase + h + q * (J + 1)) * npad + atom] = s;
+                Y[(size_t)atom * nhalf + row->ebase + h + q * (J + 1)] = s;
                 const double2 uv = U[(size_t)(row->frow + h * (J + 1) + q) * npad + atom];
                 e += (s.x * uv.x + s.y * uv.y) * row->einv[h][q];
             }
@@ -453,7 +453,7 @@ hipError_t launch_y_t(int n, int npad, const double2 *U, double2 *Y, const DevTa
 {
     const int nblk8 = (((n + 63) / 64) + 7) / 8 * 8;
     hipLaunchKernelGGL(k_compute_y<TJ>, dim3(T.nyrows * nblk8), dim3(64 * kYWaves), 0, s, n, npad,
-                       nblk8, U, Y, T.yrows, T.ycontrib, T.ycp, T.ycq, beta,
+                       T.nhalf, nblk8, U, Y, T.yrows, T.ycontrib, T.ycp, T.ycq, beta,
                        per_atom_beta, nb, btype, nelem, gscale, Epart);
     return hipGetLastError();
 }
@@ -468,7 +468,7 @@ hipError_t launch_y_lds_t(int n, int npad, int gi, const double2 *U, double2 *Y,
     const int nblk = (n + kYLdsAtoms - 1) / kYLdsAtoms;
     const int nblk8 = (nblk + 7) / 8 * 8;
     hipLaunchKernelGGL(k_compute_y_lds<TJ>, dim3(nblk8 * G), dim3(64 * kYLdsWaves), 0, s, n, npad,
-                       G, U, Y, T.yrows, T.yltask + T.yl_task_off[gi],
+                       T.nhalf, G, U, Y, T.yrows, T.yltask + T.yl_task_off[gi],
                        T.ylgroup + T.yl_group_off[gi], T.ylcontrib, T.ylcp, T.ycq, beta,
                        per_atom_beta, nb, btype, nelem, gscale, Epart);
     return hipGetLastError();

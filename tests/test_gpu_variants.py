@@ -1,0 +1,84 @@
+"""GPU parity of the selectable kernel variants (snap_params.y_kernel,
+snap_params.dedr_dirs) against the CPU oracle, on every atom and pair.
+
+Tolerances as in test_gpu_parity: energies within 1e-11 relative to
+max(|E_i|, mean |E_i|), forces and pair derivatives within 1e-10 eV/A.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2011_12875_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+E_REL = 1e-11
+F_ABS = 1e-10
+
+
+def _compare(pos, box, beta, tj, **kw):
+    import torch
+    from paper_2011_12875_amd import snapmi
+    pot = snapmi.SnapPotential(tj, wl.RCUT, **kw)
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    tpos = torch.as_tensor(pos, device="cuda")
+    tbeta = torch.as_tensor(beta, device="cuda")
+    out = pot.compute(tpos, box, nl, tbeta, bispectrum=False, pair_derivs=True)
+    pot.sync_status()
+    E = out["energy"].cpu().numpy()
+    F = out["force"].cpu().numpy()
+    dE = out["dE"].cpu().numpy()
+    o = oracle.snap(pos, box, tj, wl.RCUT, beta=beta)
+    scale = np.maximum(np.abs(o["E"]), np.abs(o["E"]).mean())
+    assert (np.abs(E - o["E"]) / scale).max() <= E_REL
+    assert np.abs(F - o["F"]).max() <= F_ABS
+    off, nbr = nl.off.cpu().numpy(), nl.nbr.cpu().numpy()[:nl.npairs]
+    gm = {(i, int(nbr[t])): t for i in range(len(off) - 1) for t in range(off[i], off[i + 1])}
+    om = {(i, int(o["nbr"][t])): t for i in range(len(o["off"]) - 1)
+          for t in range(o["off"][i], o["off"][i + 1])}
+    assert gm.keys() == om.keys()
+    keys = list(om)
+    assert np.abs(dE[[gm[k] for k in keys]] - o["dE"][[om[k] for k in keys]]).max() <= F_ABS
+
+
+@pytest.mark.parametrize("y_kernel", [1, 2])
+@pytest.mark.parametrize("name", ["bcc128_2j4", "bcc2000_2j8"])
+def test_y_kernel_variants(name, y_kernel):
+    pos, box, beta, tj = wl.make(name)
+    print("case", name, "y_kernel", y_kernel, flush=True)
+    _compare(pos, box, beta, tj, y_kernel=y_kernel)
+
+
+@pytest.mark.parametrize("tj", [2, 3, 5, 6, 7])
+def test_y_lds_small(tj):
+    pos, box = wl.bcc(3, 0.1, 40 + tj)
+    beta = wl.beta(wl.ncoeff(tj), 50 + tj)
+    print("case twojmax", tj, "y_kernel 2", flush=True)
+    _compare(pos, box, beta, tj, y_kernel=2)
+
+
+@pytest.mark.parametrize("dirs", [1, 3])
+@pytest.mark.parametrize("name", ["bcc128_2j4", "bcc2000_2j8"])
+def test_dedr_dirs_variants(name, dirs):
+    pos, box, beta, tj = wl.make(name)
+    print("case", name, "dedr_dirs", dirs, flush=True)
+    _compare(pos, box, beta, tj, dedr_dirs=dirs)
+
+
+@pytest.mark.parametrize("kern", [1, 2, 3, 4])
+@pytest.mark.parametrize("name", ["bcc128_2j4", "bcc2000_2j8"])
+def test_dedr_kernel_variants(name, kern):
+    pos, box, beta, tj = wl.make(name)
+    print("case", name, "dedr_kernel", kern, flush=True)
+    _compare(pos, box, beta, tj, dedr_kernel=kern)
+
+
+@pytest.mark.parametrize("kern", [2, 3, 4])
+@pytest.mark.parametrize("tj", [0, 1, 2, 3, 5, 6, 7, 9, 10, 11, 12, 13, 14])
+def test_dedr_generator_every_twojmax(tj, kern):
+    """Every template instance of the generator form (straight-line and looped
+    levels, one and two wavefronts per block, staged and unstaged Y~)."""
+    pos, box = wl.bcc(3, 0.1, 60 + tj)
+    beta = wl.beta(wl.ncoeff(tj), 70 + tj)
+    print("case twojmax", tj, "dedr_kernel", kern, flush=True)
+    _compare(pos, box, beta, tj, dedr_kernel=kern)
