@@ -310,6 +310,47 @@ def surrogate_leg(epochs, steps, warmup, log=None):
     }
 
 
+def surrogate_decay_study(decays, epochs, log=None):
+    """The same network, data and training on targets whose components above
+    J = 4 are damped by decay ** ((J - 4) / 2): decay 0 makes the target
+    exactly linear in the 2J = 4 bispectrum (the surrogate's inputs), so the
+    error left there is the training's own; decay 1 is the undamped draw.
+    Force RMSE on the test configurations and on the 16 000-atom
+    configuration, next to the best linear 2J = 4 fit."""
+    import torch
+    from paper_2011_12875_amd import snapmi
+    from paper_2011_12875_amd import surrogate as sg
+    from paper_2011_12875_amd import workloads as wl
+    pot4 = snapmi.SnapPotential(4, wl.RCUT, wl.RFAC0, wl.RMIN0, 1)
+    pot8 = snapmi.SnapPotential(8, wl.RCUT, wl.RFAC0, wl.RMIN0, 1)
+    tr, va, te = wl.surrogate_split()
+    pos, box = wl.surrogate_inference_config()
+    nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
+    tpos = torch.as_tensor(pos, device="cuda")
+    rows = []
+    for decay in decays:
+        beta8 = wl.surrogate_target_beta(decay)
+        dtr = sg.make_surrogate_data(tr, pot8, beta8, pot4)
+        dva = sg.make_surrogate_data(va, pot8, beta8, pot4)
+        dte = sg.make_surrogate_data(te, pot8, beta8, pot4)
+        net, hist = sg.train(dtr, sg.TrainConfig(epochs=epochs), dva)
+        test = sg.evaluate(net, dte)
+        lin = sg.evaluate_linear(*sg.fit_linear(dtr), dte)
+        ref_rms = float(dte.F.pow(2).mean().sqrt())
+        del dtr, dva, dte
+        judge = sg.SurrogatePotential(net, pot4, pot8, beta8).judge(tpos, box, nl)
+        row = {"decay": decay, "test_force_rmse_meV_per_A": 1e3 * test["force_rmse"],
+               "test_linear_2j4_force_rmse_meV_per_A": 1e3 * lin["force_rmse"],
+               "test_ref_force_rms_eV_per_A": ref_rms,
+               "infer16000_force_rmse_meV_per_A": 1e3 * judge["force_rmse"],
+               "infer16000_ref_force_rms_eV_per_A": judge["ref_force_rms"],
+               "val_history": hist}
+        if log:
+            log({k: v for k, v in row.items() if k != "val_history"})
+        rows.append(row)
+    return {"epochs": epochs, "rows": rows}
+
+
 METRIC_LABEL = {
     "bcc128_2j4": "atom-steps/s SNAP E+F at 2J=4, 128 atoms",
     "bcc2000_2j8": "atom-steps/s SNAP E+F at 2J=8, 2000 atoms",
@@ -352,6 +393,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="bcc2000_2j8", choices=sorted(METRIC_LABEL))
     ap.add_argument("--dedr-dirs", type=int, default=0)
+    ap.add_argument("--dedr-waves", type=int, default=0,
+                    help="generator form: wavefronts per block of 64 pairs (0 auto, 1 .. 4)")
     ap.add_argument("--u-kernel", type=int, default=0,
                     help="compute_U variant: 0 auto, 1 column workgroups, 2 one pair per lane")
     ap.add_argument("--dedr-kernel", type=int, default=0,
@@ -370,6 +413,10 @@ def main():
                     help="only time the surrogate's inference step on the 16 000-atom "
                          "configuration with a seeded, untrained network and the range gate "
                          "off (a kernel-trace target), print one JSON line and exit")
+    ap.add_argument("--surrogate-decays", default="", metavar="D1,D2,...",
+                    help="train the surrogate on targets with the components above J = 4 "
+                         "damped by each given factor, print one JSON line with the force "
+                         "errors and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device 3 times (a kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -388,6 +435,13 @@ def main():
     if args.surrogate_step:
         print(json.dumps(surrogate_step_timing(args.steps, args.warmup)), flush=True)
         return
+    if args.surrogate_decays:
+        decays = [float(x) for x in args.surrogate_decays.split(",")]
+        res = surrogate_decay_study(decays, args.surrogate_epochs,
+                                    log=lambda r: print("surrogate", json.dumps(r),
+                                                        file=sys.stderr, flush=True))
+        print(json.dumps(res), flush=True)
+        return
 
     elements = args.workload in wl.ELEMENT_WORKLOADS
     quadratic = args.workload.endswith("_quad")
@@ -398,7 +452,7 @@ def main():
     n = len(pos)
     pot = snapmi.SnapPotential(tj, wl.RCUT, wl.RFAC0, wl.RMIN0, 1, dedr_dirs=args.dedr_dirs,
                                y_kernel=args.y_kernel, dedr_kernel=args.dedr_kernel,
-                               u_kernel=args.u_kernel)
+                               dedr_waves=args.dedr_waves, u_kernel=args.u_kernel)
     nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
     tpos = torch.as_tensor(pos, device="cuda")
     tbeta = torch.as_tensor(beta, device="cuda")
@@ -486,7 +540,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "atoms": n, "pairs": nl.npairs, "twojmax": tj,
                    "u_kernel": args.u_kernel, "y_kernel": args.y_kernel,
-                   "dedr_kernel": args.dedr_kernel,
+                   "dedr_kernel": args.dedr_kernel, "dedr_waves": args.dedr_waves,
                    "dedr_dirs": args.dedr_dirs,
                    "ncoeff": pot.ncoeff, "rcut": wl.RCUT, "rfac0": wl.RFAC0,
                    "lattice": "bcc a=3.1803 A", "parallelism": "single GPU"},

@@ -79,6 +79,9 @@ typedef struct {
                         * 2J = 5, the columns split over two wavefronts, 3 as
                         * 2 with Y~ read through the texture path, 4 as 2 with
                         * one wavefront per block of pairs                   */
+    int dedr_waves;    /* generator form: wavefronts that split the columns
+                        * of a block of 64 pairs, 1 .. 4 (0: auto, 1 up to
+                        * 2J = 4, else 2)                                    */
     int u_kernel;      /* compute_U variant: 0 auto (1), 1 one workgroup per
                         * column of the stored half (two pairs per lane, seed
                         * paths), 2 one pair per lane walking every column   */

@@ -317,6 +317,7 @@ static int check_params(const snap_params *p)
     if (p->y_kernel < 0 || p->y_kernel > 2) return fail(SNAP_EINVAL, "y_kernel must be 0, 1 or 2");
     if (p->dedr_kernel < 0 || p->dedr_kernel > 4)
         return fail(SNAP_EINVAL, "dedr_kernel must be 0 .. 4");
+    if (p->dedr_waves < 0 || p->dedr_waves > 4) return fail(SNAP_EINVAL, "dedr_waves must be 0 .. 4");
     if (p->u_kernel < 0 || p->u_kernel > 2) return fail(SNAP_EINVAL, "u_kernel must be 0, 1 or 2");
     return SNAP_OK;
 }
@@ -365,8 +366,8 @@ static hipError_t run_dedr(const snap_ctx *c, int n, int npairs, int, const doub
     if (k == 1)
         return launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, c->tab.nhalf, pos, nbr,
                            pair_atom, Y, c->dev, g, dE, s);
-    return launch_dedr_gen(c->prm.twojmax, k - 2, npairs, c->tab.nhalf, pos, nbr, pair_atom, Y,
-                           g, dE, s);
+    return launch_dedr_gen(c->prm.twojmax, k == 3 ? 1 : 0, k == 4 ? 1 : c->prm.dedr_waves, npairs,
+                           c->tab.nhalf, pos, nbr, pair_atom, Y, g, dE, s);
 }
 
 extern "C" {
@@ -405,6 +406,7 @@ int snap_setup(int twojmax, double rcut, double rfac0, double rmin0, int switch_
     p.dedr_dirs = 0;
     p.y_kernel = 0;
     p.dedr_kernel = 0;
+    p.dedr_waves = 0;
     p.u_kernel = 0;
     return snap_setup_ex(&p, out);
 }

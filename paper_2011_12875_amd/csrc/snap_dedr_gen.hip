@@ -54,6 +54,11 @@ struct YRow {
     __device__ __forceinline__ double2 get(int e) const { return p[e]; }
 };
 
+// Above 2J = 10 the levels of a column run in a loop (straight-line code for
+// every level would not fit the instruction cache).
+template <int TJ>
+constexpr bool kGenStraight = TJ <= 10;
+
 // MIR: the level may carry the mirror term (J = 2C + 1 or 2C + 2), which
 // indexes the column at J - p: J must then be a compile-time constant.
 template <int TJ, bool MIR, class YS>
@@ -106,6 +111,9 @@ __device__ __forceinline__ void gen_level(int C, int J, GenState<TJ> &st, double
                 trr += sg * (yr.x * w.x - yr.y * w.y);
                 tri += sg * (yr.x * w.y + yr.y * w.x);
             }
+            // at most two rows of Y~ reads in flight (hoisted, the reads of a
+            // whole level would hold ~100 registers)
+            if (kGenStraight<TJ> && (p & 1)) memory_fence_compiler();
         }
     st.S0 += t0r;
     const double w0 = (double)(J - 2 * C);
@@ -127,11 +135,6 @@ __device__ __forceinline__ void gen_level(int C, int J, GenState<TJ> &st, double
         st.Ap.y += wr * tri;
     }
 }
-
-// Above 2J = 10 the levels of a column run in a loop (straight-line code for
-// every level would not fit the instruction cache).
-template <int TJ>
-constexpr bool kGenStraight = TJ <= 10;
 
 // Column C walked in full: levels max(1, 2C) .. TJ with their terms.
 template <int TJ, int C, class YS>
@@ -193,11 +196,11 @@ __device__ __forceinline__ void gen_columns(GenState<TJ> &st, double2 a, double2
     if constexpr (C + 1 < CE) gen_columns<TJ, C + 1, CB, CE>(st, a, b, ys);
 }
 
-// Split of the columns between two wavefronts (the first walks columns
-// 0 .. split - 1, the second runs their seed paths and walks the rest): the
-// split with the smallest larger share, an element of a walk costing about
-// 2.5 times one of a seed path (three multiply-adds of Y~ on top of the
-// recursion).
+// Split of the columns over NR wavefronts: wavefront r walks the columns
+// [col_begin(TJ, NR, r), col_begin(TJ, NR, r + 1)) after the seed paths of
+// the columns before them.  The split minimises the largest share, an element
+// of a walk costing about 2.5 times one of a seed path (three multiply-adds
+// of Y~ on top of the recursion).
 constexpr int col_elems(int TJ, int c)
 {
     int e = 0;
@@ -210,24 +213,49 @@ constexpr int seed_elems(int c)
     for (int J = (c == 0 ? 1 : 2 * c); J <= 2 * c + 1; ++J) e += J + 1;
     return e;
 }
-constexpr int col_split(int TJ)
+// cost of a wavefront walking columns [b, e)
+constexpr int role_cost(int TJ, int b, int e)
 {
-    int best = 1, bc = 1 << 30;
-    for (int cs = 1; cs <= TJ / 2; ++cs) {
-        int c0 = 0, c1 = 0;
-        for (int c = 0; c < cs; ++c) {
-            c0 += 5 * col_elems(TJ, c);
-            c1 += 2 * seed_elems(c);
-        }
-        for (int c = cs; c <= TJ / 2; ++c) c1 += 5 * col_elems(TJ, c);
-        const int m = c0 > c1 ? c0 : c1;
-        if (m < bc) {
-            bc = m;
-            best = cs;
+    int c0 = 0;
+    for (int c = 0; c < b; ++c) c0 += 2 * seed_elems(c);
+    for (int c = b; c < e; ++c) c0 += 5 * col_elems(TJ, c);
+    return c0;
+}
+struct ColSplit {
+    int b[5];
+};
+constexpr ColSplit col_split(int TJ, int NR)
+{
+    const int nc = TJ / 2 + 1;
+    const int nr = NR < nc ? NR : nc;  // wavefronts with columns; the rest idle
+    ColSplit best{{0, nc, nc, nc, nc}};
+    if (nr <= 1) return best;
+    int bc = 1 << 30;
+    // boundaries 0 < b1 < b2 < b3 < nc (as many as nr - 1)
+    for (int b1 = 1; b1 < nc; ++b1) {
+        for (int b2 = b1 + 1; b2 <= nc; ++b2) {
+            if ((nr > 2) != (b2 < nc)) continue;
+            for (int b3 = b2 + 1; b3 <= nc + 1; ++b3) {
+                const int c3 = b3 > nc ? nc : b3;
+                if ((nr > 3) != (b3 < nc)) continue;
+                const int bb[5] = {0, b1, b2 > nc ? nc : b2, c3, nc};
+                int m = 0;
+                for (int r = 0; r < 4; ++r)
+                    if (bb[r] < bb[r + 1]) {
+                        const int cst = role_cost(TJ, bb[r], bb[r + 1]);
+                        m = cst > m ? cst : m;
+                    }
+                if (m < bc) {
+                    bc = m;
+                    best = ColSplit{{bb[0], bb[1], bb[2], bb[3], bb[4]}};
+                }
+            }
         }
     }
     return best;
 }
+template <int TJ, int NR, int R>
+constexpr int kColB = col_split(TJ, NR).b[R];
 
 // The sums of one pair over columns [CB, CE) (the J = 0 term with the first
 // column), for the wavefront's role.
@@ -238,7 +266,7 @@ __device__ __forceinline__ void gen_sums(const PairGeom &pg, const YS &ys, GenSt
     for (int p = 0; p <= TJ; ++p) st.seed[p] = make_double2(0.0, 0.0);
     st.A0 = st.Ap = st.Am = make_double2(0.0, 0.0);
     st.S0 = (CB == 0) ? ys.get(0).x : 0.0;  // J = 0: poly = 1
-    if constexpr (TJ >= 1) gen_columns<TJ, 0, CB, CE>(st, pg.a, pg.b, ys);
+    if constexpr (TJ >= 1 && CB < CE) gen_columns<TJ, 0, CB, CE>(st, pg.a, pg.b, ys);
 }
 
 // dE for the three directions from the sums.
@@ -280,16 +308,38 @@ constexpr int kStageAtoms = (kStageBytes / (16 * hbase_of(TJ + 1)) > 16)  ? 16
                             : (kStageBytes / (16 * hbase_of(TJ + 1)) < 4) ? 4
                                                                           : kStageBytes / (16 * hbase_of(TJ + 1));
 
-// Workgroup = 64 consecutive pairs, one lane per pair, NR wavefronts: with
-// NR = 2 the columns are split between the two (col_split) and the second
-// wavefront's sums are added to the first's through LDS.  Workgroup w runs
-// on XCD w % 8 and takes logical block (w % 8) * per + w / 8, so each XCD
-// walks a contiguous eighth of the pairs.  The pairs of a block belong to
-// the atoms pair_atom[first] .. [last] (the list is grouped by atom); when
-// they fit (STAGE), their rows of Y~, one contiguous range of the
-// atom-major array, are copied to LDS and every element is read from there
-// (about 2.5 reads per element of the walk; a vector load costs about three
-// times an LDS read).  Otherwise the lanes read Y~ from global memory.
+// The sums of the columns of wavefront R (compile-time bounds), dispatched
+// on the wavefront's uniform index.
+template <int TJ, int NR, int R, class YS>
+__device__ __forceinline__ void role_sums(int role, const PairGeom &pg, const YS &ys,
+                                          GenState<TJ> &st)
+{
+    if constexpr (R < NR) {
+        if (role == R) {
+            constexpr int b = kColB<TJ, NR, R>, e = kColB<TJ, NR, R + 1>;
+            if constexpr (b < e) {
+                gen_sums<TJ, b, e>(pg, ys, st);
+            } else {
+                // no columns for this wavefront (more wavefronts than columns)
+                st.A0 = st.Ap = st.Am = make_double2(0.0, 0.0);
+                st.S0 = 0.0;
+            }
+        } else {
+            role_sums<TJ, NR, R + 1>(role, pg, ys, st);
+        }
+    }
+}
+
+// Workgroup = 64 consecutive pairs, one lane per pair, NR wavefronts that
+// split the columns (col_split); the sums of wavefronts 1 .. NR - 1 are added
+// to wavefront 0's through LDS in a fixed order.  Workgroup w runs on XCD
+// w % 8 and takes logical block (w % 8) * per + w / 8, so each XCD walks a
+// contiguous eighth of the pairs.  The pairs of a block belong to the atoms
+// pair_atom[first] .. [last] (the list is grouped by atom); when they fit
+// (STAGE), their rows of Y~, one contiguous range of the atom-major array,
+// are copied to LDS and every element is read from there (about 2.5 reads
+// per element of the walk; a vector load costs about three times an LDS
+// read).  Otherwise the lanes read Y~ from global memory.
 template <int TJ, bool STAGE, int NR>
 __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
                                                       const double *__restrict__ pos,
@@ -299,10 +349,9 @@ __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
                                                       double *__restrict__ dE)
 {
     constexpr int NST = STAGE ? kStageAtoms<TJ> * hbase_of(TJ + 1) : 1;
-    constexpr int CS = (NR == 2) ? col_split(TJ) : TJ / 2 + 1;
-    constexpr int NC = TJ / 2 + 1;
     __shared__ double2 yl[NST];
-    __shared__ double part[NR == 2 ? 7 : 1][64];
+    // sums of wavefronts 1 .. NR - 1, [NR - 1][7][64]
+    __shared__ double part[(NR > 1 ? (NR - 1) * 7 * 64 : 1)];
     const int nblk = (npairs + 63) / 64;
     const int per = (nblk + 7) / 8;
     const int w = (int)blockIdx.x;
@@ -321,6 +370,21 @@ __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
     pair_cut(g, i, k, rc, wk);
     PairGeom pg;
     const bool ok = pair_geometry(rv, g, rc, wk, pg);
+    // the geometry the last step needs waits in LDS during the walk (only the
+    // Cayley-Klein pair stays in registers)
+    __shared__ double keep[9][64];
+    if (role == 0) {
+        keep[0][lane] = pg.n[0];
+        keep[1][lane] = pg.n[1];
+        keep[2][lane] = pg.n[2];
+        keep[3][lane] = pg.r;
+        keep[4][lane] = pg.c0;
+        keep[5][lane] = pg.s0;
+        keep[6][lane] = pg.dth0;
+        keep[7][lane] = pg.fc;
+        keep[8][lane] = pg.dfdr;
+    }
+    memory_fence_compiler();
     GenState<TJ> st;
     bool staged = false;
     if constexpr (STAGE) {
@@ -335,40 +399,45 @@ __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
             // (i - afirst is in range for a list grouped by atom; clamped so
             // that no other list can read outside the staged rows)
             const int ia = min(max(i - afirst, 0), alast - afirst);
-            const YRow ys{yl + ia * nh};
-            if (role == 0)
-                gen_sums<TJ, 0, CS>(pg, ys, st);
-            else
-                gen_sums<TJ, CS, NC>(pg, ys, st);
+            role_sums<TJ, NR, 0>(role, pg, YRow{yl + ia * nh}, st);
         }
     }
-    if (!staged) {
-        const YRow ys{Y + (size_t)i * nh};
-        if (role == 0)
-            gen_sums<TJ, 0, CS>(pg, ys, st);
-        else
-            gen_sums<TJ, CS, NC>(pg, ys, st);
-    }
-    if constexpr (NR == 2) {
-        if (role == 1) {
-            part[0][lane] = st.S0;
-            part[1][lane] = st.A0.x;
-            part[2][lane] = st.A0.y;
-            part[3][lane] = st.Ap.x;
-            part[4][lane] = st.Ap.y;
-            part[5][lane] = st.Am.x;
-            part[6][lane] = st.Am.y;
+    if (!staged) role_sums<TJ, NR, 0>(role, pg, YRow{Y + (size_t)i * nh}, st);
+    if constexpr (NR > 1) {
+        if (role > 0) {
+            double *pr = &part[(role - 1) * 7 * 64];
+            pr[0 * 64 + lane] = st.S0;
+            pr[1 * 64 + lane] = st.A0.x;
+            pr[2 * 64 + lane] = st.A0.y;
+            pr[3 * 64 + lane] = st.Ap.x;
+            pr[4 * 64 + lane] = st.Ap.y;
+            pr[5 * 64 + lane] = st.Am.x;
+            pr[6 * 64 + lane] = st.Am.y;
         }
         __syncthreads();
-        if (role == 1) return;
-        st.S0 += part[0][lane];
-        st.A0.x += part[1][lane];
-        st.A0.y += part[2][lane];
-        st.Ap.x += part[3][lane];
-        st.Ap.y += part[4][lane];
-        st.Am.x += part[5][lane];
-        st.Am.y += part[6][lane];
+        if (role > 0) return;
+#pragma unroll
+        for (int r = 0; r < NR - 1; ++r) {
+            const double *pr = &part[r * 7 * 64];
+            st.S0 += pr[0 * 64 + lane];
+            st.A0.x += pr[1 * 64 + lane];
+            st.A0.y += pr[2 * 64 + lane];
+            st.Ap.x += pr[3 * 64 + lane];
+            st.Ap.y += pr[4 * 64 + lane];
+            st.Am.x += pr[5 * 64 + lane];
+            st.Am.y += pr[6 * 64 + lane];
+        }
     }
+    memory_fence_compiler();
+    pg.n[0] = keep[0][lane];
+    pg.n[1] = keep[1][lane];
+    pg.n[2] = keep[2][lane];
+    pg.r = keep[3][lane];
+    pg.c0 = keep[4][lane];
+    pg.s0 = keep[5][lane];
+    pg.dth0 = keep[6][lane];
+    pg.fc = keep[7][lane];
+    pg.dfdr = keep[8][lane];
     double d[3];
     gen_finish<TJ>(pg, ok, st, d);
     if (valid) {
@@ -378,33 +447,37 @@ __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
     }
 }
 
-// Wavefronts per block of 64 pairs: two from 2J = 5 on (the walk is long
-// enough to split), else one.
+// Wavefronts per block of 64 pairs (the columns split over them): one up to
+// 2J = 4, where the walk is short, two above.
 template <int TJ>
 constexpr int kGenRoles = TJ >= 5 ? 2 : 1;
 
+template <int TJ, bool STAGE, int NR>
+void launch_gen_nr(int ngrid, hipStream_t s, int npairs, int nh, const double *pos, const int *nbr,
+                   const int *pair_atom, const double2 *Y, const Geom &g, double *dE)
+{
+    hipLaunchKernelGGL((k_dedr_gen<TJ, STAGE, NR>), dim3(ngrid), dim3(64 * NR), 0, s, npairs, nh,
+                       pos, nbr, pair_atom, Y, g, dE);
+}
+
 template <int TJ>
-hipError_t launch_gen_t(int mapping, int npairs, int nh, const double *pos, const int *nbr,
-                        const int *pair_atom, const double2 *Y, const Geom &g, double *dE,
-                        hipStream_t s)
+hipError_t launch_gen_t(int mapping, int waves, int npairs, int nh, const double *pos,
+                        const int *nbr, const int *pair_atom, const double2 *Y, const Geom &g,
+                        double *dE, hipStream_t s)
 {
     // one workgroup per 64 pairs, padded to a multiple of 8 (the padding exits)
     const int nblk = (npairs + 63) / 64;
     const int ngrid = ((nblk + 7) / 8) * 8;
-    constexpr int R = kGenRoles<TJ>;
-    switch (mapping) {
-    case 0:
-        hipLaunchKernelGGL((k_dedr_gen<TJ, true, R>), dim3(ngrid), dim3(64 * R), 0, s, npairs, nh,
-                           pos, nbr, pair_atom, Y, g, dE);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_dedr_gen<TJ, false, R>), dim3(ngrid), dim3(64 * R), 0, s, npairs,
-                           nh, pos, nbr, pair_atom, Y, g, dE);
-        break;
-    default:
-        hipLaunchKernelGGL((k_dedr_gen<TJ, true, 1>), dim3(ngrid), dim3(64), 0, s, npairs, nh, pos,
-                           nbr, pair_atom, Y, g, dE);
-        break;
+    const int nr = waves > 0 ? waves : kGenRoles<TJ>;
+    if (mapping == 1) {
+        launch_gen_nr<TJ, false, kGenRoles<TJ>>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE);
+        return hipGetLastError();
+    }
+    switch (nr) {
+    case 1: launch_gen_nr<TJ, true, 1>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
+    case 2: launch_gen_nr<TJ, true, 2>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
+    case 3: launch_gen_nr<TJ, true, 3>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
+    default: launch_gen_nr<TJ, true, 4>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
     }
     return hipGetLastError();
 }
@@ -416,13 +489,13 @@ hipError_t launch_gen_t(int mapping, int npairs, int nh, const double *pos, cons
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 #endif
 
-hipError_t launch_dedr_gen(int twojmax, int mapping, int npairs, int nh, const double *pos,
-                           const int *nbr, const int *pair_atom, const double2 *Y, const Geom &g,
-                           double *dE, hipStream_t s)
+hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int npairs, int nh,
+                           const double *pos, const int *nbr, const int *pair_atom,
+                           const double2 *Y, const Geom &g, double *dE, hipStream_t s)
 {
     switch (twojmax) {
 #define X(k) \
-    case k: return launch_gen_t<k>(mapping, npairs, nh, pos, nbr, pair_atom, Y, g, dE, s);
+    case k: return launch_gen_t<k>(mapping, waves, npairs, nh, pos, nbr, pair_atom, Y, g, dE, s);
         SNAP_TJ_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

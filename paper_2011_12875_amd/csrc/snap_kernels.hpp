@@ -97,11 +97,12 @@ inline hipError_t launch_dedr(int twojmax, int dirs, int npairs, int npad, const
 }
 
 // compute_dE in the generator form (snap_dedr_gen.hip): mapping 0 with the
-// block's rows of Y~ staged in LDS, 1 read through the texture path, 2 staged
-// with one wavefront per block; nh = row length of the atom-major Y~
-hipError_t launch_dedr_gen(int twojmax, int mapping, int npairs, int nh, const double *pos,
-                           const int *nbr, const int *pair_atom, const double2 *Y, const Geom &g,
-                           double *dE, hipStream_t s);
+// block's rows of Y~ staged in LDS, 1 read through the texture path; waves =
+// wavefronts per block of 64 pairs (0: auto); nh = row length of the
+// atom-major Y~
+hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int npairs, int nh,
+                           const double *pos, const int *nbr, const int *pair_atom,
+                           const double2 *Y, const Geom &g, double *dE, hipStream_t s);
 
 hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *rev,
                          const double *dE, const double *Epart, double *energy, double *force,

@@ -42,7 +42,7 @@ class snap_params(ctypes.Structure):
                 ("rmin0", ctypes.c_double), ("switch_flag", ctypes.c_int),
                 ("wself", ctypes.c_double), ("dedr_dirs", ctypes.c_int),
                 ("y_kernel", ctypes.c_int), ("dedr_kernel", ctypes.c_int),
-                ("u_kernel", ctypes.c_int)]
+                ("dedr_waves", ctypes.c_int), ("u_kernel", ctypes.c_int)]
 
 
 _lib = None
@@ -167,11 +167,11 @@ class SnapPotential:
     """One parameter set of the potential (a library context)."""
 
     def __init__(self, twojmax, rcut, rfac0=0.99363, rmin0=0.0, switch_flag=1, wself=1.0,
-                 dedr_dirs=0, y_kernel=0, dedr_kernel=0, u_kernel=0):
+                 dedr_dirs=0, y_kernel=0, dedr_kernel=0, dedr_waves=0, u_kernel=0):
         lib = load()
         p = snap_params(int(twojmax), float(rcut), float(rfac0), float(rmin0), int(switch_flag),
                         float(wself), int(dedr_dirs), int(y_kernel), int(dedr_kernel),
-                        int(u_kernel))
+                        int(dedr_waves), int(u_kernel))
         ctx = ctypes.c_void_p()
         _check(lib.snap_setup_ex(ctypes.byref(p), ctypes.byref(ctx)))
         self._ctx = ctx

@@ -82,3 +82,55 @@ def test_dedr_generator_every_twojmax(tj, kern):
     beta = wl.beta(wl.ncoeff(tj), 70 + tj)
     print("case twojmax", tj, "dedr_kernel", kern, flush=True)
     _compare(pos, box, beta, tj, dedr_kernel=kern)
+
+
+@pytest.mark.parametrize("kern", [1, 2])
+@pytest.mark.parametrize("name", ["bcc128_2j4", "bcc2000_2j8"])
+def test_u_kernel_variants(name, kern):
+    pos, box, beta, tj = wl.make(name)
+    print("case", name, "u_kernel", kern, flush=True)
+    _compare(pos, box, beta, tj, u_kernel=kern)
+
+
+@pytest.mark.parametrize("tj", [0, 1, 2, 3, 5, 6, 7, 9, 10, 11, 12, 13, 14])
+def test_u_lane_every_twojmax(tj):
+    pos, box = wl.bcc(3, 0.1, 80 + tj)
+    beta = wl.beta(wl.ncoeff(tj), 90 + tj)
+    print("case twojmax", tj, "u_kernel 2", flush=True)
+    _compare(pos, box, beta, tj, u_kernel=2)
+
+
+def test_u_lane_long_neighbour_lists():
+    """More than 32 neighbours per atom (several chunks of lanes per atom):
+    a dense cluster with a cutoff that takes in ~60 neighbours."""
+    rng = np.random.default_rng(7)
+    n = 150
+    pos = rng.uniform(0.0, 9.0, (n, 3))
+    box = np.array([0.0, 0.0, 0.0])
+    tj = 6
+    beta = wl.beta(wl.ncoeff(tj), 11)
+    import torch
+    from paper_2011_12875_amd import snapmi
+    rcut = 4.5
+    pot = snapmi.SnapPotential(tj, rcut, u_kernel=2)
+    nl = snapmi.NeighborList.build(pos, box, rcut)
+    counts = np.diff(nl.off.cpu().numpy())
+    assert counts.max() > 32, counts.max()
+    out = pot.compute(torch.as_tensor(pos, device="cuda"), box, nl,
+                      torch.as_tensor(beta, device="cuda"))
+    pot.sync_status()
+    o = oracle.snap(pos, box, tj, rcut, beta=beta, want_dE=False)
+    E, F = out["energy"].cpu().numpy(), out["force"].cpu().numpy()
+    scale = np.maximum(np.abs(o["E"]), np.abs(o["E"]).mean())
+    assert (np.abs(E - o["E"]) / scale).max() <= E_REL
+    assert np.abs(F - o["F"]).max() <= F_ABS
+
+
+@pytest.mark.parametrize("waves", [1, 2, 3, 4])
+@pytest.mark.parametrize("tj", [4, 8, 14])
+def test_dedr_waves(tj, waves):
+    """The generator form with the columns split over 1 .. 4 wavefronts."""
+    pos, box = wl.bcc(3, 0.1, 100 + tj)
+    beta = wl.beta(wl.ncoeff(tj), 110 + tj)
+    print("case twojmax", tj, "dedr_waves", waves, flush=True)
+    _compare(pos, box, beta, tj, dedr_kernel=2, dedr_waves=waves)
