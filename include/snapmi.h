@@ -161,6 +161,25 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
                  int per_atom_beta, double *energy, double *force, double *bispec,
                  double *dE_pair, void *stream);
 
+/* snap_compute without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * snap_compute; the workspace (U, Y, per-row energy shares, pair derivatives
+ * unless dE_pair is given, pair->atom map) is carved from one static device
+ * array of 64 MiB per GPU, held until the process ends (2000 atoms at
+ * 2J = 14 fit; the call needs about 16 (N_full + N_half) npad + 8 rows npad
+ * + 28 npairs bytes).  The call allocates nothing: the context's constant
+ * tables must already be on the device (one earlier snap_compute or
+ * snap_forward on this context, on the current device), else SNAP_EINVAL;
+ * sizes beyond the array are refused with SNAP_EINVAL.  Every call on a GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams,
+ * other threads) race; it does not change the workspace snap_backward and
+ * snap_copy_workspace use. */
+int snap_compute_noalloc(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                         const int *off, const int *nbr, const int *rev, const double *beta,
+                         int per_atom_beta, double *energy, double *force, double *bispec,
+                         double *dE_pair, void *stream);
+
 /* Quadratic SNAP: the energy of eq. (snapatomenergy) extended to second
  * order in the bispectrum,
  *   E_i = beta . B_i + (1/2) B_i^T alpha B_i,

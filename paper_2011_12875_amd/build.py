@@ -26,6 +26,7 @@ UNITS = [
     ("snap_dedr_gen.hip", [], "snap_dedr_gen.o"),
     ("snap_misc.hip", [], "snap_misc.o"),
     ("snap_mlp.hip", [], "snap_mlp.o"),
+    ("snap_static.hip", [], "snap_static.o"),
 ]
 
 FLAGS = [

@@ -628,6 +628,76 @@ int snap_compute(snap_ctx *c, int n, int npairs, const double *pos, const double
                         energy, force, bispec, dE_pair, stream);
 }
 
+int snap_compute_noalloc(snap_ctx *c, int n, int npairs, const double *pos, const double box[3],
+                         const int *off, const int *nbr, const int *rev, const double *beta,
+                         int per_atom_beta, double *energy, double *force, double *bispec,
+                         double *dE_pair, void *stream)
+{
+    int st = common_checks(c, n, npairs, pos, box, off, nbr, rev, beta);
+    if (st) return st;
+    if (n > 0 && (!energy || !force)) return fail(SNAP_EINVAL, "NULL output pointer");
+    if (!c->dev_ready)
+        return fail(SNAP_EINVAL,
+                    "the context's tables are not on the device yet: one allocating call "
+                    "(snap_compute or snap_forward) on this context must come first");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != c->device)
+        return fail(SNAP_EDEV, "context tables are on device %d, current device is %d", c->device,
+                    dev);
+    if (n == 0) return SNAP_OK;
+    // the workspace carved from the static array: U (element-major, full
+    // matrices), Y (atom-major half), Epart, dE (unless the caller takes it),
+    // pair->atom map, each 256-byte aligned
+    const int npad = (n + 63) / 64 * 64;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t bU = al(sizeof(double2) * (size_t)c->tab.nfullel * npad);
+    const size_t bY = al(sizeof(double2) * (size_t)c->tab.nhalf * npad);
+    const size_t bE = al(sizeof(double) * c->tab.yrows.size() * npad);
+    const size_t bD = dE_pair ? 0 : al(sizeof(double) * 3 * (size_t)(npairs > 0 ? npairs : 1));
+    const size_t bP = al(sizeof(int) * (size_t)(npairs > 0 ? npairs : 1));
+    const size_t need = bU + bY + bE + bD + bP;
+    if (need > static_scratch_bytes())
+        return fail(SNAP_EINVAL,
+                    "n = %d, %d pairs at twojmax %d need %zu bytes of workspace; the static "
+                    "workspace holds %zu",
+                    n, npairs, c->prm.twojmax, need, static_scratch_bytes());
+    void *base = nullptr;
+    HIP_TRY(static_scratch(&base), "hipGetSymbolAddress of the static workspace");
+    unsigned char *b = (unsigned char *)base;
+    Work w;
+    w.U = (double2 *)b;
+    w.Y = (double2 *)(b + bU);
+    w.Epart = (double *)(b + bU + bY);
+    w.dE = dE_pair ? dE_pair : (double *)(b + bU + bY + bE);
+    w.pair_atom = (int *)(b + bU + bY + bE + bD);
+    w.flag = c->work.flag;
+    w.npad = npad;
+    hipStream_t s = (hipStream_t)stream;
+    Geom g = make_geom(c, box);
+    const int nb = c->tab.nb;
+    // the array keeps the previous call's contents: the padding atoms, which
+    // the kernels read but never write, start from zero
+    HIP_TRY(launch_zero_padding(w.U, c->tab.nfullel, w.Y, c->tab.nhalf, n, npad, s),
+            "workspace padding");
+    HIP_TRY(launch_compute_u(c->prm.twojmax, c->prm.u_kernel ? c->prm.u_kernel : 1, n, npad, pos,
+                             off, nbr, c->dev, g, w.U, w.pair_atom, w.flag, s),
+            "compute_U launch");
+    HIP_TRY(launch_compute_y(c->prm.twojmax, n, npad, w.U, w.Y, c->dev, beta, per_atom_beta, nb,
+                             nullptr, 0, nullptr, w.Epart, s),
+            "compute_Y launch");
+    if (npairs > 0)
+        HIP_TRY(run_dedr(c, n, npairs, npad, pos, off, nbr, w.pair_atom, w.Y, g, w.dE, s),
+                "compute_dE launch");
+    HIP_TRY(launch_gather(n, npad, c->dev.nyrows, off, rev, w.dE, w.Epart, energy, force, s),
+            "update_forces launch");
+    if (bispec)
+        HIP_TRY(launch_bispectrum(n, npad, w.U, c->dev, nb, bispec, beta, per_atom_beta, nullptr,
+                                  s, c->tab.nfullel),
+                "bispectrum launch");
+    return SNAP_OK;
+}
+
 int snap_compute_quadratic(snap_ctx *c, int n, int npairs, const double *pos,
                            const double box[3], const int *off, const int *nbr, const int *rev,
                            const double *beta, const double *alpha, double *energy,

@@ -104,6 +104,14 @@ hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int npairs, int 
                            const double *pos, const int *nbr, const int *pair_atom,
                            const double2 *Y, const Geom &g, double *dE, hipStream_t s);
 
+// the static workspace of snap_compute_noalloc (snap_static.hip): its size,
+// this device's address of it (looked up once per device), and the zeroing of
+// the padding atoms of U (element-major) and Y (atom-major)
+size_t static_scratch_bytes();
+hipError_t static_scratch(void **out);
+hipError_t launch_zero_padding(double2 *U, int nfull, double2 *Y, int nhalf, int n, int npad,
+                               hipStream_t s);
+
 hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *rev,
                          const double *dE, const double *Epart, double *energy, double *force,
                          hipStream_t s);

@@ -23,6 +23,7 @@ ERRORS = {-1: "SNAP_EINVAL", -2: "SNAP_EBOX", -3: "SNAP_ENBR", -4: "SNAP_EGEOM",
 # every symbol include/snapmi.h declares
 EXPORTS = ["snap_setup", "snap_setup_ex", "snap_destroy", "snap_ncoeff", "snap_nhalf",
            "snap_table", "snap_build_neighbors", "snap_check_neighbors", "snap_compute",
+           "snap_compute_noalloc",
            "snap_forward", "snap_backward", "snap_copy_workspace", "snap_profile",
            "snap_stage_times", "snap_sync_status", "snap_last_error",
            "snap_mlp_nparams", "snap_mlp_workspace", "snap_mlp_forward", "snap_mlp_grad",
@@ -68,6 +69,7 @@ def load():
         "snap_build_neighbors": (i, [dp, i, dp, d, ip, ip, ip, i, ip]),
         "snap_check_neighbors": (i, [i, ip, ip, ip, i]),
         "snap_compute": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp, vp]),
+        "snap_compute_noalloc": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp, vp, vp]),
         "snap_set_elements": (i, [vp, i, dp, dp, d]),
         "snap_compute_elements": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "snap_forward": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, i, vp, vp, vp]),
@@ -263,6 +265,19 @@ class SnapPotential:
             self._ptr(out["force"]), self._ptr(out.get("bispectrum")), self._ptr(out.get("dE")),
             self._stream()))
         self._fwd_token += 1  # U of this call replaces that of the last forward
+        return out
+
+    def compute_noalloc(self, pos, box, nl, beta, out, bispectrum=False, pair_derivs=False):
+        """As compute(), through snap_compute_noalloc: the library allocates no
+        device memory (its workspace is a static array).  The caller passes
+        the output tensors (out["energy"], out["force"], and out["bispectrum"]
+        / out["dE"] when asked for)."""
+        n, boxa, per_atom = self._args(pos, box, nl, beta)
+        _check(load().snap_compute_noalloc(
+            self._ctx, n, nl.npairs, self._ptr(pos), boxa, self._ptr(nl.off), self._ptr(nl.nbr),
+            self._ptr(nl.rev), self._ptr(beta), per_atom, self._ptr(out["energy"]),
+            self._ptr(out["force"]), self._ptr(out["bispectrum"] if bispectrum else None),
+            self._ptr(out["dE"] if pair_derivs else None), self._stream()))
         return out
 
     def compute_quadratic(self, pos, box, nl, beta, alpha, bispectrum=False, pair_derivs=False,
