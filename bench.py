@@ -205,14 +205,16 @@ def cpu_baseline(workload):
     return head
 
 
-def surrogate_step_timing(steps, warmup):
+def surrogate_step_timing(steps, warmup, variants=None):
     """The surrogate's inference step alone (2J = 4 descriptors, network, 2J = 4
     adjoint stages), no gate read-back, on the 16 000-atom configuration; the
     network is seeded but untrained: the kernels and their cost do not depend
-    on the weights."""
+    on the weights.  variants: kernel choices (snap_params fields) of the
+    2J = 4 potential."""
     import torch
     from paper_2011_12875_amd import snapmi, surrogate as sg, workloads as wl
-    pot4, pot8 = snapmi.SnapPotential(4, wl.RCUT), snapmi.SnapPotential(8, wl.RCUT)
+    pot4 = snapmi.SnapPotential(4, wl.RCUT, **(variants or {}))
+    pot8 = snapmi.SnapPotential(8, wl.RCUT)
     pos, box = wl.surrogate_inference_config()
     nl = snapmi.NeighborList.build(pos, box, wl.RCUT)
     tpos = torch.as_tensor(pos, device="cuda")
@@ -229,7 +231,7 @@ def surrogate_step_timing(steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     return {"surrogate_step_ms": ms, "atoms": len(pos), "pairs": nl.npairs, "steps": steps,
-            "note": "untrained seeded network, range gate off"}
+            "variants_2j4": variants or {}, "note": "untrained seeded network, range gate off"}
 
 
 def surrogate_leg(epochs, steps, warmup, log=None):
@@ -285,14 +287,27 @@ def surrogate_leg(epochs, steps, warmup, log=None):
     ms_plain = timed(lambda: pot8.compute(tpos, box, nl, tb8, out=out8))
     ms_sur = timed(lambda: sp.compute(tpos, box, nl, check=True))
     ms_sur_nocheck = timed(lambda: sp.compute(tpos, box, nl, check=False))
+    # the read-back of each step's gate settled while the next step runs
+    pending = [None]
+
+    def deferred_step():
+        out = sp.compute(tpos, box, nl, check="deferred")
+        if pending[0] is not None:
+            assert not sp.resolve(pending[0])["fallback"]
+        pending[0] = out
+
+    ms_sur_deferred = timed(deferred_step)
+    sp.resolve(pending[0])
     pos_o, box_o = wl.surrogate_inference_config(ood=True)
     nl_o = snapmi.NeighborList.build(pos_o, box_o, wl.RCUT)
     ood = sp.compute(torch.as_tensor(pos_o, device="cuda"), box_o, nl_o)
     rmse_mev = judge["force_rmse"] * 1e3
     return {
         "speedup": ms_plain / ms_sur,
+        "speedup_gate_readback_deferred": ms_plain / ms_sur_deferred,
         "speedup_without_gate_readback": ms_plain / ms_sur_nocheck,
         "ms_plain_2j8": ms_plain, "ms_surrogate": ms_sur,
+        "ms_surrogate_deferred_check": ms_sur_deferred,
         "atoms": n, "force_rmse_meV_per_A": rmse_mev,
         "meets_30meV_per_A": bool(rmse_mev <= 30.0),
         "ref_force_rms_eV_per_A": judge["ref_force_rms"],
@@ -396,7 +411,8 @@ def main():
     ap.add_argument("--dedr-waves", type=int, default=0,
                     help="generator form: wavefronts per block of 64 pairs (0 auto, 1 .. 4)")
     ap.add_argument("--u-kernel", type=int, default=0,
-                    help="compute_U variant: 0 auto, 1 column workgroups, 2 one pair per lane")
+                    help="compute_U variant: 0 auto, 1 column workgroups, 2 one pair per lane, "
+                         "3 lanes over the elements of a level")
     ap.add_argument("--dedr-kernel", type=int, default=0,
                     help="compute_dE variant: 0 auto, 1 tangent form, 2 generator form (Y~ in "
                          "LDS), 3 generator form (Y~ through the texture path), 4 generator "
@@ -433,7 +449,9 @@ def main():
     from paper_2011_12875_amd import workloads as wl
 
     if args.surrogate_step:
-        print(json.dumps(surrogate_step_timing(args.steps, args.warmup)), flush=True)
+        variants = {k: getattr(args, k) for k in ("u_kernel", "y_kernel", "dedr_kernel",
+                                                  "dedr_waves", "dedr_dirs")}
+        print(json.dumps(surrogate_step_timing(args.steps, args.warmup, variants)), flush=True)
         return
     if args.surrogate_decays:
         decays = [float(x) for x in args.surrogate_decays.split(",")]

@@ -84,7 +84,9 @@ typedef struct {
                         * 2J = 4, else 2)                                    */
     int u_kernel;      /* compute_U variant: 0 auto (1), 1 one workgroup per
                         * column of the stored half (two pairs per lane, seed
-                        * paths), 2 one pair per lane walking every column   */
+                        * paths), 2 one pair per lane walking every column,
+                        * 3 lanes over the elements of a level, one wavefront
+                        * per atom, level J - 1 in LDS (Sec. VI)            */
 } snap_params;
 
 /* Create a context for one parameter set.  Builds the host index tables
@@ -334,10 +336,13 @@ long long snap_mlp_workspace(int nin, int n);
  *           outside [lo - margin (hi - lo), hi + margin (hi - lo)] or is not
  *           finite, *ood_flag is set to 1 (it is never cleared here).
  *   ood_flag int[1] or NULL.
+ *   clear_flag int[1] or NULL: set to 0 by the launch, for the next call
+ *           (two flags used alternately need no separate clearing; it must
+ *           not be ood_flag).
  * Errors: SNAP_EINVAL, SNAP_EDEV. */
 int snap_mlp_forward(int nin, int n, const float *params, const float *norm,
                      const float *bounds, float margin, const double *bispec, double *energy,
-                     double *grad_b, int *ood_flag, void *stream);
+                     double *grad_b, int *ood_flag, int *clear_flag, void *stream);
 
 /* Parameter gradient of  Phi = sum_i dl_de_i E_i + dl_dg_i . g_i  (grad,
  * float[nparams], overwritten): back-propagation for the first term,

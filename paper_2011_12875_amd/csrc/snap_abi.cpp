@@ -318,7 +318,7 @@ static int check_params(const snap_params *p)
     if (p->dedr_kernel < 0 || p->dedr_kernel > 4)
         return fail(SNAP_EINVAL, "dedr_kernel must be 0 .. 4");
     if (p->dedr_waves < 0 || p->dedr_waves > 4) return fail(SNAP_EINVAL, "dedr_waves must be 0 .. 4");
-    if (p->u_kernel < 0 || p->u_kernel > 2) return fail(SNAP_EINVAL, "u_kernel must be 0, 1 or 2");
+    if (p->u_kernel < 0 || p->u_kernel > 3) return fail(SNAP_EINVAL, "u_kernel must be 0 .. 3");
     return SNAP_OK;
 }
 
@@ -1016,8 +1016,10 @@ long long snap_mlp_workspace(int nin, int n)
 
 int snap_mlp_forward(int nin, int n, const float *params, const float *norm,
                      const float *bounds, float margin, const double *bispec, double *energy,
-                     double *grad_b, int *ood_flag, void *stream)
+                     double *grad_b, int *ood_flag, int *clear_flag, void *stream)
 {
+    if (clear_flag && clear_flag == ood_flag)
+        return fail(SNAP_EINVAL, "clear_flag must differ from ood_flag");
     if (n < 0 || n > (1 << 24)) return fail(SNAP_EINVAL, "n out of range");
     if (!std::isfinite(margin) || margin < 0.0f) return fail(SNAP_EINVAL, "margin must be >= 0");
     int st = check_free_call(nin);
@@ -1026,7 +1028,7 @@ int snap_mlp_forward(int nin, int n, const float *params, const float *norm,
     if (!params || !norm || !bispec || !energy || !grad_b)
         return fail(SNAP_EINVAL, "NULL pointer argument");
     HIP_TRY(launch_mlp_forward(nin, n, params, norm, bounds, margin, bispec, energy, grad_b,
-                               ood_flag, (hipStream_t)stream),
+                               ood_flag, clear_flag, (hipStream_t)stream),
             "network forward launch");
     return SNAP_OK;
 }

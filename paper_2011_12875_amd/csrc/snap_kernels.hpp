@@ -62,7 +62,8 @@ struct Work {
     int npad = 0;
 };
 
-// variant 1: one workgroup per column of the stored half; 2: one pair per lane
+// variant 1: one workgroup per column of the stored half; 2: one pair per lane;
+// 3: lanes over the elements of a level
 hipError_t launch_compute_u(int twojmax, int variant, int n, int npad, const double *pos,
                             const int *off, const int *nbr, const DevTables &T, const Geom &g,
                             double2 *U, int *pair_atom, int *flag, hipStream_t s);
@@ -151,7 +152,7 @@ size_t mlp_grad_workspace(int nin, int n);
 
 hipError_t launch_mlp_forward(int nin, int n, const float *prm, const float *norm,
                               const float *bounds, float margin, const double *B, double *E,
-                              double *g, int *flag, hipStream_t s);
+                              double *g, int *flag, int *clear_flag, hipStream_t s);
 hipError_t launch_mlp_grad(int nin, int n, const float *prm, const float *norm, const double *B,
                            const double *rE, const double *v, float *work, float *grad,
                            hipStream_t s);

@@ -75,9 +75,12 @@ template <int NIN>
 __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward_w(
     int n, const float *__restrict__ prm, const float *__restrict__ norm,
     const float *__restrict__ bounds, float margin, const double *__restrict__ B,
-    double *__restrict__ E, double *__restrict__ g, int *__restrict__ flag)
+    double *__restrict__ E, double *__restrict__ g, int *__restrict__ flag,
+    int *__restrict__ clear_flag)
 {
     using L = MlpLayout<NIN>;
+    // the flag of the next call (no workgroup of this launch touches it)
+    if (clear_flag && blockIdx.x == 0 && threadIdx.x == 0) clear_flag[0] = 0;
     __shared__ float a1s[H][64];               // a1 of the block's atoms
     __shared__ float part[kFwdWaves][H][64];   // per-wave partial dE/da1, then dE/dx
     __shared__ float es[kFwdWaves][64];        // per-wave partial energies
@@ -489,11 +492,11 @@ size_t mlp_grad_workspace(int nin, int n)
 
 hipError_t launch_mlp_forward(int nin, int n, const float *prm, const float *norm,
                               const float *bounds, float margin, const double *B, double *E,
-                              double *g, int *flag, hipStream_t s)
+                              double *g, int *flag, int *clear_flag, hipStream_t s)
 {
 #define CALL(K)                                                                              \
     hipLaunchKernelGGL(k_mlp_forward_w<K>, dim3((n + 63) / 64), dim3(64 * kFwdWaves), 0, s, n, \
-                       prm, norm, bounds, margin, B, E, g, flag)
+                       prm, norm, bounds, margin, B, E, g, flag, clear_flag)
     SNAP_MLP_DISPATCH(nin, CALL)
 #undef CALL
     return hipGetLastError();

@@ -476,6 +476,112 @@ __global__ __launch_bounds__(64) void k_compute_u2(int n, int npad, const double
     }
 }
 
+// ---------------------------------------------------------------------------
+// compute_U, lanes over the elements of a level (the mapping of the paper's
+// Sec. VI, kept as a measured alternative)
+//
+// One wavefront per atom walks its pairs one after another.  For each pair,
+// level J of the recursion is computed by the lanes, one stored element
+// (p, q) each (lane = q (J + 1) + p, at most 45 at 2J = 8), from level J - 1
+// held in LDS as a full matrix; each lane writes its element and the mirror
+// image back for level J + 1 and adds it to its running sum of that element
+// over the atom's pairs (registers, one per level).  The pair geometry is
+// computed by the lanes for up to 64 pairs at a time and read back from LDS
+// as wavefront-uniform values.
+// ---------------------------------------------------------------------------
+template <int TJ>
+__global__ __launch_bounds__(64) void k_compute_u3(int n, int npad, const double *__restrict__ pos,
+                                                   const int *__restrict__ off,
+                                                   const int *__restrict__ nbr, Geom g,
+                                                   const UInfo *__restrict__ uinfo,
+                                                   double2 *__restrict__ U,
+                                                   int *__restrict__ pair_atom,
+                                                   int *__restrict__ flag)
+{
+    constexpr int LW = (TJ + 1) * (TJ + 1);
+    // stored elements per lane and level: (J + 1)(J/2 + 1) <= 120 at 2J = 14
+    constexpr int M = ((TJ + 1) * (TJ / 2 + 1) + 63) / 64;
+    __shared__ double2 lv[2][LW > 1 ? LW : 1];
+    __shared__ double geo[5][64];  // a.x, a.y, b.x, b.y, f_c of 64 pairs
+    const int i = (int)blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int beg = off[i], end = off[i + 1];
+    double2 acc[TJ + 1][M];
+#pragma unroll
+    for (int J = 0; J <= TJ; ++J)
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[J][m] = make_double2(0.0, 0.0);
+    for (int c0 = beg; c0 < end; c0 += 64) {
+        const int t = c0 + lane;
+        PairGeom pg;
+        slot_geometry(t < end, i, t, true, pos, nbr, g, pair_atom, flag, pg);
+        __syncthreads();  // the previous chunk's reads of geo are done
+        geo[0][lane] = pg.a.x;
+        geo[1][lane] = pg.a.y;
+        geo[2][lane] = pg.b.x;
+        geo[3][lane] = pg.b.y;
+        geo[4][lane] = pg.fc;
+        __syncthreads();
+        const int cnt = min(64, end - c0);
+        for (int k = 0; k < cnt; ++k) {
+            const double2 a = make_double2(geo[0][k], geo[1][k]);
+            const double2 b = make_double2(geo[2][k], geo[3][k]);
+            const double fc = geo[4][k];
+            // level 0: poly = f_c (the recursion is linear in its start)
+            if (lane == 0) {
+                lv[0][0] = make_double2(fc, 0.0);
+                acc[0][0].x += fc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int J = 1; J <= TJ; ++J) {
+                const double2 *prev = lv[(J - 1) & 1];  // level J - 1: J x J, row-major
+                double2 *cur = lv[J & 1];               // level J: (J+1) x (J+1)
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int e = lane + 64 * m;
+                    if (e < (J + 1) * (J / 2 + 1)) {
+                        const int q = e / (J + 1), p = e - q * (J + 1);
+                        double nr = 0.0, ni = 0.0;
+                        if (p < J) {
+                            const double2 u = prev[p * J + q];
+                            nr = a.x * u.x + a.y * u.y;
+                            ni = a.x * u.y - a.y * u.x;
+                        }
+                        if (p > 0) {
+                            const double2 w = prev[(p - 1) * J + q];
+                            nr = nr - b.x * w.x - b.y * w.y;
+                            ni = ni - b.x * w.y + b.y * w.x;
+                        }
+                        acc[J][m].x += nr;
+                        acc[J][m].y += ni;
+                        const double sg = ((p - q) & 1) ? -1.0 : 1.0;
+                        cur[p * (J + 1) + q] = make_double2(nr, ni);
+                        cur[(J - p) * (J + 1) + (J - q)] = make_double2(sg * nr, -sg * ni);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // the atom's sums, as full matrices of true values (w_self on the diagonal)
+#pragma unroll
+    for (int J = 0; J <= TJ; ++J)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = lane + 64 * m;
+            if (e < (J + 1) * (J / 2 + 1)) {
+                const int q = e / (J + 1), p = e - q * (J + 1);
+                const UInfo ui = uinfo[hbase_of(J) + e];
+                const double2 v = make_double2((p == q ? g.wself : 0.0) + ui.nrm * acc[J][m].x,
+                                               ui.nrm * acc[J][m].y);
+                U[(size_t)ui.fi * npad + i] = v;
+                if (ui.fm >= 0)
+                    U[(size_t)ui.fm * npad + i] = make_double2(ui.msign * v.x, -ui.msign * v.y);
+            }
+        }
+}
+
 template <int TJ>
 hipError_t launch_u_t(int variant, int n, int npad, const double *pos, const int *off,
                       const int *nbr, const Geom &g, const UInfo *uinfo, double2 *U,
@@ -484,6 +590,11 @@ hipError_t launch_u_t(int variant, int n, int npad, const double *pos, const int
     if (variant == 2) {
         hipLaunchKernelGGL(k_compute_u2<TJ>, dim3((n + 1) / 2), dim3(64), 0, s, n, npad, pos, off,
                            nbr, g, uinfo, U, pair_atom, flag);
+        return hipGetLastError();
+    }
+    if (variant == 3) {
+        hipLaunchKernelGGL(k_compute_u3<TJ>, dim3(n), dim3(64), 0, s, n, npad, pos, off, nbr, g,
+                           uinfo, U, pair_atom, flag);
         return hipGetLastError();
     }
     const int nblk = ((n + kUAtoms - 1) / kUAtoms) * kUGroups<TJ>;

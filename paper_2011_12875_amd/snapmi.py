@@ -84,7 +84,7 @@ def load():
         "snap_last_error": (ctypes.c_char_p, []),
         "snap_mlp_nparams": (i, [i]),
         "snap_mlp_workspace": (ctypes.c_longlong, [i, i]),
-        "snap_mlp_forward": (i, [i, i, vp, vp, vp, f, vp, vp, vp, vp, vp]),
+        "snap_mlp_forward": (i, [i, i, vp, vp, vp, f, vp, vp, vp, vp, vp, vp]),
         "snap_mlp_grad": (i, [i, i, vp, vp, vp, vp, vp, vp, vp, vp]),
         "snap_adam_step": (i, [i, vp, vp, vp, vp, f, f, f, f, i, vp]),
         "snap_jacobian": (i, [vp, i, i, vp, dp, vp, vp, vp, vp, vp, vp]),
@@ -475,9 +475,9 @@ def mlp_workspace(nin, n):
 
 
 def mlp_forward(params, norm, bispec, bounds=None, margin=0.0, flag=None, energy=None,
-                grad_b=None):
+                grad_b=None, clear_flag=None):
     """(E_i, g_i = dE_i/dB_i) of the network; sets flag[0] = 1 on inputs
-    outside the bounds widened by margin."""
+    outside the bounds widened by margin, and clear_flag[0] = 0."""
     import torch
     n, nin = bispec.shape
     _dev(params, torch.float32, (mlp_nparams(nin),))
@@ -487,11 +487,14 @@ def mlp_forward(params, norm, bispec, bounds=None, margin=0.0, flag=None, energy
         _dev(bounds, torch.float32, (2, nin))
     if flag is not None:
         _dev(flag, torch.int32)
+    if clear_flag is not None:
+        _dev(clear_flag, torch.int32)
     E = energy if energy is not None else torch.empty(n, dtype=torch.float64, device=bispec.device)
     g = grad_b if grad_b is not None else torch.empty((n, nin), dtype=torch.float64,
                                                       device=bispec.device)
     _check(load().snap_mlp_forward(nin, n, _p(params), _p(norm), _p(bounds), float(margin),
-                                   _p(bispec), _p(E), _p(g), _p(flag), _stream()))
+                                   _p(bispec), _p(E), _p(g), _p(flag), _p(clear_flag),
+                                   _stream()))
     return E, g
 
 

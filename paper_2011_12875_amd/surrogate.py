@@ -73,10 +73,10 @@ class Network:
         norm = np.stack([np.asarray(mean, dtype=np.float64), scale])
         return cls(torch.tensor(p, device=device), torch.tensor(norm, device=device))
 
-    def forward(self, B, flag=None, energy=None, grad_b=None, gate=True):
+    def forward(self, B, flag=None, energy=None, grad_b=None, gate=True, clear_flag=None):
         return snapmi.mlp_forward(self.params, self.norm, B,
                                   self.bounds if gate else None, self.margin, flag,
-                                  energy, grad_b)
+                                  energy, grad_b, clear_flag)
 
     def state(self):
         return {"params": self.params.cpu().numpy(), "norm": self.norm.cpu().numpy(),
@@ -338,13 +338,23 @@ def evaluate_linear(beta, const, data: Dataset, batch_configs=200):
 class SurrogatePotential:
     """E and F from the network on 2J = 4 descriptors; configurations with
     descriptors outside the training range (widened by the margin) fall back
-    to plain SNAP with the target coefficients at the high order."""
+    to plain SNAP with the target coefficients at the high order.
+
+    The range gate writes one of two device flags, alternately: the network
+    kernel sets this call's flag and clears the other one for the next call,
+    so no separate clearing kernel runs.  The flag is copied to pinned host
+    memory behind the step on the same stream; compute(check=True) waits for
+    it, compute(check="deferred") returns at once with the check pending and
+    resolve() settles it later (a fallback evaluation replaces the result if
+    the gate tripped), so that the host never waits inside a step."""
 
     def __init__(self, net: Network, pot4, pot8, beta8):
         import torch
         self.net, self.pot4, self.pot8 = net, pot4, pot8
         self.beta8 = torch.as_tensor(np.asarray(beta8, dtype=np.float64), device="cuda")
-        self.flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.flags = torch.zeros(2, dtype=torch.int32, device="cuda")
+        self.host_flags = torch.zeros(2, dtype=torch.int32).pin_memory()
+        self.slot = 0
         self._bufs = {}
 
     def _buffers(self, n):
@@ -358,18 +368,41 @@ class SurrogatePotential:
         return self._bufs
 
     def compute(self, pos, box, nl, check=True):
-        """Returns {"energy", "force", "fallback"}.  With check=False the gate
-        is still evaluated on the device but not read back (the caller reads
-        self.flag later)."""
+        """Returns {"energy", "force", "fallback"}.  check=True: the gate is
+        read back (the host waits for the step) and a tripped gate gives the
+        fallback result; check="deferred": the read-back is enqueued and the
+        result carries it as "pending" (see resolve); check=False: the gate
+        is evaluated on the device but not read."""
+        import torch
         b = self._buffers(pos.shape[0])
-        self.flag.zero_()
+        s = self.slot
+        self.slot ^= 1
         _, B = self.pot4.forward(pos, box, nl, None, bispectrum=b["B"])
-        E, g = self.net.forward(B, flag=self.flag, energy=b["E"], grad_b=b["g"])
+        E, g = self.net.forward(B, flag=self.flags[s:s + 1], energy=b["E"], grad_b=b["g"],
+                                clear_flag=self.flags[1 - s:2 - s])
         F = self.pot4.backward(pos, box, nl, g, b["ones"], force=b["F"])
         out = {"energy": E, "force": F, "fallback": False}
-        if check and int(self.flag.item()):
+        if not check:
+            return out
+        self.host_flags[s:s + 1].copy_(self.flags[s:s + 1], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        out["pending"] = (ev, s, pos, box, nl)
+        if check == "deferred":
+            return out
+        return self.resolve(out)
+
+    def resolve(self, out):
+        """Settle a pending gate check: wait for its read-back and, if the
+        gate tripped, replace the result by plain SNAP at the high order."""
+        pend = out.pop("pending", None)
+        if pend is None:
+            return out
+        ev, s, pos, box, nl = pend
+        ev.synchronize()
+        if int(self.host_flags[s]):
             o8 = self.pot8.compute(pos, box, nl, self.beta8)
-            out = {"energy": o8["energy"], "force": o8["force"], "fallback": True}
+            out.update({"energy": o8["energy"], "force": o8["force"], "fallback": True})
         return out
 
     def judge(self, pos, box, nl, out=None):

@@ -277,6 +277,37 @@ def test_fallback_on_out_of_range_configuration():
     assert j["force_rmse"] == 0.0 and j["fallback"]
 
 
+def test_gate_flags_alternate_and_deferred_check():
+    """The two gate flags: an in-range, an out-of-range, then an in-range
+    configuration again (the tripped flag is cleared by the call after the
+    next, without any clearing kernel), each checked with the deferred
+    read-back; the out-of-range one resolves to plain 2J = 8 SNAP."""
+    torch, snapmi = _torch()
+    from paper_2011_12875_amd import surrogate as sg
+    pot4, pot8 = snapmi.SnapPotential(4, wl.RCUT), snapmi.SnapPotential(8, wl.RCUT)
+    beta8 = wl.surrogate_target_beta()
+    Btr = np.concatenate([oracle.snap(wl.surrogate_config(c)[0], wl.surrogate_config(c)[1], 4,
+                                      wl.RCUT, beta=np.zeros(14), want_dE=False)["B"]
+                          for c in range(6)])
+    net = _untrained_surrogate(torch, snapmi, Btr)
+    net.margin = 0.05
+    sp = sg.SurrogatePotential(net, pot4, pot8, beta8)
+    pin, bin_, _ = wl.surrogate_config(0)
+    nl_in = snapmi.NeighborList.build(pin, bin_, wl.RCUT)
+    pout, bout = wl.bcc(10, wl.SURROGATE["sigma_ood"], wl.SURROGATE["ood_seed"])
+    nl_out = snapmi.NeighborList.build(pout, bout, wl.RCUT)
+    tin, tout = torch.tensor(pin, device="cuda"), torch.tensor(pout, device="cuda")
+    seq = [(tin, bin_, nl_in, False), (tout, bout, nl_out, True), (tin, bin_, nl_in, False),
+           (tin, bin_, nl_in, False), (tout, bout, nl_out, True), (tout, bout, nl_out, True),
+           (tin, bin_, nl_in, False)]
+    for tpos, box, nl, want in seq:
+        out = sp.resolve(sp.compute(tpos, box, nl, check="deferred"))
+        assert out["fallback"] == want
+        if want:
+            ref = pot8.compute(tpos, box, nl, torch.tensor(beta8, device="cuda"))
+            assert torch.equal(out["force"], ref["force"])
+
+
 def test_training_reduces_loss_and_beats_linear_model():
     """A short training (1000 configurations, 4000 Adam steps): the held-out
     force error falls, and the trained network beats the linear 2J = 4 model

@@ -84,7 +84,7 @@ def test_dedr_generator_every_twojmax(tj, kern):
     _compare(pos, box, beta, tj, dedr_kernel=kern)
 
 
-@pytest.mark.parametrize("kern", [1, 2])
+@pytest.mark.parametrize("kern", [1, 2, 3])
 @pytest.mark.parametrize("name", ["bcc128_2j4", "bcc2000_2j8"])
 def test_u_kernel_variants(name, kern):
     pos, box, beta, tj = wl.make(name)
@@ -92,17 +92,20 @@ def test_u_kernel_variants(name, kern):
     _compare(pos, box, beta, tj, u_kernel=kern)
 
 
+@pytest.mark.parametrize("kern", [2, 3])
 @pytest.mark.parametrize("tj", [0, 1, 2, 3, 5, 6, 7, 9, 10, 11, 12, 13, 14])
-def test_u_lane_every_twojmax(tj):
+def test_u_lane_every_twojmax(tj, kern):
     pos, box = wl.bcc(3, 0.1, 80 + tj)
     beta = wl.beta(wl.ncoeff(tj), 90 + tj)
-    print("case twojmax", tj, "u_kernel 2", flush=True)
-    _compare(pos, box, beta, tj, u_kernel=2)
+    print("case twojmax", tj, "u_kernel", kern, flush=True)
+    _compare(pos, box, beta, tj, u_kernel=kern)
 
 
-def test_u_lane_long_neighbour_lists():
-    """More than 32 neighbours per atom (several chunks of lanes per atom):
-    a dense cluster with a cutoff that takes in ~60 neighbours."""
+@pytest.mark.parametrize("kern", [1, 2, 3])
+def test_u_long_neighbour_lists(kern):
+    """More than 32 neighbours per atom (several chunks of lanes per atom;
+    more than 64 for the lanes-over-elements variant): a dense cluster with a
+    cutoff that takes in up to 75 neighbours."""
     rng = np.random.default_rng(7)
     n = 150
     pos = rng.uniform(0.0, 9.0, (n, 3))
@@ -112,7 +115,7 @@ def test_u_lane_long_neighbour_lists():
     import torch
     from paper_2011_12875_amd import snapmi
     rcut = 4.5
-    pot = snapmi.SnapPotential(tj, rcut, u_kernel=2)
+    pot = snapmi.SnapPotential(tj, rcut, u_kernel=kern)
     nl = snapmi.NeighborList.build(pos, box, rcut)
     counts = np.diff(nl.off.cpu().numpy())
     assert counts.max() > 32, counts.max()
