@@ -198,6 +198,7 @@ static int ensure_device(snap_ctx *c)
     }
     d.nyrows = (int)t.yrows.size();
     d.nhalf = t.nhalf;
+    d.ncu = prop.multiProcessorCount;
     if (!t.ylcontrib.empty() && c->prm.y_kernel != 1) {
         HIP_TRY(upload(d.ylcontrib, t.ylcontrib), "upload ylcontrib");
         HIP_TRY(upload(d.ylcp, t.ylcp), "upload ylcp");
@@ -366,8 +367,8 @@ static hipError_t run_dedr(const snap_ctx *c, int n, int npairs, int, const doub
     if (k == 1)
         return launch_dedr(c->prm.twojmax, dedr_dirs(c), npairs, c->tab.nhalf, pos, nbr,
                            pair_atom, Y, c->dev, g, dE, s);
-    return launch_dedr_gen(c->prm.twojmax, k == 3 ? 1 : 0, k == 4 ? 1 : c->prm.dedr_waves, npairs,
-                           c->tab.nhalf, pos, nbr, pair_atom, Y, g, dE, s);
+    return launch_dedr_gen(c->prm.twojmax, k == 3 ? 1 : 0, k == 4 ? 1 : c->prm.dedr_waves,
+                           c->dev.ncu, npairs, c->tab.nhalf, pos, nbr, pair_atom, Y, g, dE, s);
 }
 
 extern "C" {

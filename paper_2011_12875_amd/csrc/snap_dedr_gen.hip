@@ -33,6 +33,8 @@
 //
 // One lane per pair; the rows of Y~ the wavefront needs are staged in LDS
 // (or, as a measured alternative, read through the texture path).
+#include <algorithm>
+
 #include "snap_device.hpp"
 
 namespace snapmi {
@@ -88,28 +90,37 @@ __device__ __forceinline__ void gen_level(int C, int J, GenState<TJ> &st, double
         if (p <= J) {
             const double2 u = st.col[p];
             const double2 y0 = ys.get(eb + C * (J + 1) + p);
-            // Y~ conj(u)
-            t0r += y0.x * u.x + y0.y * u.y;
-            t0i += y0.y * u.x - y0.x * u.y;
+            // Y~ conj(u), each component a running sum of fused multiply-adds
+            t0r = fma(y0.x, u.x, t0r);
+            t0r = fma(y0.y, u.y, t0r);
+            t0i = fma(y0.y, u.x, t0i);
+            t0i = fma(-y0.x, u.y, t0i);
             if (has_m) {
                 const double2 ym = ys.get(eb + (C - 1) * (J + 1) + p);
-                tmr += ym.x * u.x + ym.y * u.y;
-                tmi += ym.y * u.x - ym.x * u.y;
+                tmr = fma(ym.x, u.x, tmr);
+                tmr = fma(ym.y, u.y, tmr);
+                tmi = fma(ym.y, u.x, tmi);
+                tmi = fma(-ym.x, u.y, tmi);
             }
             double2 yr = y0;
             if (has_p) {
                 const double2 yp = ys.get(eb + (C + 1) * (J + 1) + p);
-                tpr += yp.x * u.x + yp.y * u.y;
-                tpi += yp.y * u.x - yp.x * u.y;
+                tpr = fma(yp.x, u.x, tpr);
+                tpr = fma(yp.y, u.y, tpr);
+                tpi = fma(yp.y, u.x, tpi);
+                tpi = fma(-yp.x, u.y, tpi);
                 yr = yp;
             }
             if (MIR && (mir_even || mir_odd)) {
                 // Y~_{p,q} poly_{J-p,C} (no conjugate): the mirror rule gives
-                // poly_{p,q+1} = (-1)^(J-p-C) conj(poly_{J-p,C})
+                // poly_{p,q+1} = (-1)^(J-p-C) conj(poly_{J-p,C}); the sign is
+                // a compile-time constant folded into the operands
                 const double2 w = st.col[J - p];
                 const double sg = ((J - p - C) & 1) ? -1.0 : 1.0;
-                trr += sg * (yr.x * w.x - yr.y * w.y);
-                tri += sg * (yr.x * w.y + yr.y * w.x);
+                trr = fma(sg * yr.x, w.x, trr);
+                trr = fma(-sg * yr.y, w.y, trr);
+                tri = fma(sg * yr.x, w.y, tri);
+                tri = fma(sg * yr.y, w.x, tri);
             }
             // at most two rows of Y~ reads in flight (hoisted, the reads of a
             // whole level would hold ~100 registers)
@@ -341,7 +352,7 @@ __device__ __forceinline__ void role_sums(int role, const PairGeom &pg, const YS
 // per element of the walk; a vector load costs about three times an LDS
 // read).  Otherwise the lanes read Y~ from global memory.
 template <int TJ, bool STAGE, int NR>
-__global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
+__global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int ppb, int nh,
                                                       const double *__restrict__ pos,
                                                       const int *__restrict__ nbr,
                                                       const int *__restrict__ pair_atom,
@@ -352,16 +363,16 @@ __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
     __shared__ double2 yl[NST];
     // sums of wavefronts 1 .. NR - 1, [NR - 1][7][64]
     __shared__ double part[(NR > 1 ? (NR - 1) * 7 * 64 : 1)];
-    const int nblk = (npairs + 63) / 64;
+    const int nblk = (npairs + ppb - 1) / ppb;
     const int per = (nblk + 7) / 8;
     const int w = (int)blockIdx.x;
     const int L = (w & 7) * per + (w >> 3);
     if (L >= nblk) return;  // uniform for the workgroup
     const int role = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
-    const int t = L * 64 + lane;
-    const bool valid = t < npairs;
-    const int tt = valid ? t : npairs - 1;
+    const int t = L * ppb + lane;
+    const bool valid = lane < ppb && t < npairs;
+    const int tt = valid ? t : min(L * ppb + ppb - 1, npairs - 1);  // a pair of the block
     const int i = pair_atom[tt];
     const int k = nbr[tt];
     double rv[3];
@@ -388,8 +399,9 @@ __global__ __launch_bounds__(64 * NR) void k_dedr_gen(int npairs, int nh,
     GenState<TJ> st;
     bool staged = false;
     if constexpr (STAGE) {
-        const int afirst = __builtin_amdgcn_readfirstlane(pair_atom[L * 64]);
-        const int alast = __builtin_amdgcn_readfirstlane(pair_atom[min(L * 64 + 63, npairs - 1)]);
+        const int afirst = __builtin_amdgcn_readfirstlane(pair_atom[L * ppb]);
+        const int alast =
+            __builtin_amdgcn_readfirstlane(pair_atom[min(L * ppb + ppb - 1, npairs - 1)]);
         if (alast - afirst < kStageAtoms<TJ>) {  // uniform
             staged = true;
             const int cnt = (alast - afirst + 1) * nh;
@@ -453,31 +465,56 @@ template <int TJ>
 constexpr int kGenRoles = TJ >= 5 ? 2 : 1;
 
 template <int TJ, bool STAGE, int NR>
-void launch_gen_nr(int ngrid, hipStream_t s, int npairs, int nh, const double *pos, const int *nbr,
-                   const int *pair_atom, const double2 *Y, const Geom &g, double *dE)
+void launch_gen_nr(int ngrid, hipStream_t s, int npairs, int ppb, int nh, const double *pos,
+                   const int *nbr, const int *pair_atom, const double2 *Y, const Geom &g,
+                   double *dE)
 {
-    hipLaunchKernelGGL((k_dedr_gen<TJ, STAGE, NR>), dim3(ngrid), dim3(64 * NR), 0, s, npairs, nh,
-                       pos, nbr, pair_atom, Y, g, dE);
+    hipLaunchKernelGGL((k_dedr_gen<TJ, STAGE, NR>), dim3(ngrid), dim3(64 * NR), 0, s, npairs, ppb,
+                       nh, pos, nbr, pair_atom, Y, g, dE);
+}
+
+// Pairs per block: up to 64, as few as keep the blocks a multiple of the
+// compute-unit count (every CU then runs the same number of blocks; 51 990
+// pairs on 256 CUs: 51 per block, 4 blocks per CU, instead of 64 per block
+// with 48 CUs running a fourth block while the others idle).
+static int pairs_per_block(int npairs, int ncu)
+{
+    if (ncu <= 0) return 64;
+    const long per_round = 64L * ncu;
+    const long rounds = (npairs + per_round - 1) / per_round;
+    const long ppb = (npairs + ncu * rounds - 1) / (ncu * rounds);
+    return (int)std::max(1L, std::min(64L, ppb));
 }
 
 template <int TJ>
-hipError_t launch_gen_t(int mapping, int waves, int npairs, int nh, const double *pos,
+hipError_t launch_gen_t(int mapping, int waves, int ncu, int npairs, int nh, const double *pos,
                         const int *nbr, const int *pair_atom, const double2 *Y, const Geom &g,
                         double *dE, hipStream_t s)
 {
-    // one workgroup per 64 pairs, padded to a multiple of 8 (the padding exits)
-    const int nblk = (npairs + 63) / 64;
+    // one workgroup per block of pairs, padded to a multiple of 8 (the
+    // padding exits)
+    const int ppb = pairs_per_block(npairs, ncu);
+    const int nblk = (npairs + ppb - 1) / ppb;
     const int ngrid = ((nblk + 7) / 8) * 8;
     const int nr = waves > 0 ? waves : kGenRoles<TJ>;
     if (mapping == 1) {
-        launch_gen_nr<TJ, false, kGenRoles<TJ>>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE);
+        launch_gen_nr<TJ, false, kGenRoles<TJ>>(ngrid, s, npairs, ppb, nh, pos, nbr, pair_atom, Y,
+                                                g, dE);
         return hipGetLastError();
     }
     switch (nr) {
-    case 1: launch_gen_nr<TJ, true, 1>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
-    case 2: launch_gen_nr<TJ, true, 2>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
-    case 3: launch_gen_nr<TJ, true, 3>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
-    default: launch_gen_nr<TJ, true, 4>(ngrid, s, npairs, nh, pos, nbr, pair_atom, Y, g, dE); break;
+    case 1:
+        launch_gen_nr<TJ, true, 1>(ngrid, s, npairs, ppb, nh, pos, nbr, pair_atom, Y, g, dE);
+        break;
+    case 2:
+        launch_gen_nr<TJ, true, 2>(ngrid, s, npairs, ppb, nh, pos, nbr, pair_atom, Y, g, dE);
+        break;
+    case 3:
+        launch_gen_nr<TJ, true, 3>(ngrid, s, npairs, ppb, nh, pos, nbr, pair_atom, Y, g, dE);
+        break;
+    default:
+        launch_gen_nr<TJ, true, 4>(ngrid, s, npairs, ppb, nh, pos, nbr, pair_atom, Y, g, dE);
+        break;
     }
     return hipGetLastError();
 }
@@ -489,13 +526,14 @@ hipError_t launch_gen_t(int mapping, int waves, int npairs, int nh, const double
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 #endif
 
-hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int npairs, int nh,
+hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int ncu, int npairs, int nh,
                            const double *pos, const int *nbr, const int *pair_atom,
                            const double2 *Y, const Geom &g, double *dE, hipStream_t s)
 {
     switch (twojmax) {
 #define X(k) \
-    case k: return launch_gen_t<k>(mapping, waves, npairs, nh, pos, nbr, pair_atom, Y, g, dE, s);
+    case k:  \
+        return launch_gen_t<k>(mapping, waves, ncu, npairs, nh, pos, nbr, pair_atom, Y, g, dE, s);
         SNAP_TJ_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -34,6 +34,7 @@ struct DevTables {
     double *onehot = nullptr;  // identity [nb][nb]: unit coefficient vectors
     int nyrows = 0;
     int nhalf = 0;  // stored-half elements per atom (the row length of Y~)
+    int ncu = 0;    // compute units of the device
     // LDS-staged compute_Y (used when y_lds is set and 2J is in range)
     YLContrib *ylcontrib = nullptr;
     double *ylcp = nullptr;
@@ -99,9 +100,10 @@ inline hipError_t launch_dedr(int twojmax, int dirs, int npairs, int npad, const
 
 // compute_dE in the generator form (snap_dedr_gen.hip): mapping 0 with the
 // block's rows of Y~ staged in LDS, 1 read through the texture path; waves =
-// wavefronts per block of 64 pairs (0: auto); nh = row length of the
+// wavefronts per block of pairs (0: auto); ncu = compute units (blocks are
+// sized so that every unit runs the same number); nh = row length of the
 // atom-major Y~
-hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int npairs, int nh,
+hipError_t launch_dedr_gen(int twojmax, int mapping, int waves, int ncu, int npairs, int nh,
                            const double *pos, const int *nbr, const int *pair_atom,
                            const double2 *Y, const Geom &g, double *dE, hipStream_t s);
 

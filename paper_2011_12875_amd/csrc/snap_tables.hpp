@@ -38,7 +38,10 @@ struct UInfo {
 // Bispectrum program (eq. (z)): for a canonical l = (J1, J2, J),
 //   B_l = sum over stored (p, q) of w Re(Z(p, q) conj(U^J(p, q))),
 //   Z(p, q) = sum of terms cc U(f1) U(f2)   (full indices, true values).
-constexpr int kYWaves = 4;
+#ifndef SNAP_Y_WAVES
+#define SNAP_Y_WAVES 4
+#endif
+constexpr int kYWaves = SNAP_Y_WAVES;  // wavefronts per compute_Y workgroup
 struct BTerm {
     double cc;
     int32_t f1, f2;

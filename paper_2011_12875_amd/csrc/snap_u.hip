@@ -25,7 +25,13 @@ using namespace dev;
 // elements whatever Q is (45 at 2J = 8), so the columns are evenly loaded,
 // for 70 extra elements per pair at 2J = 8 (225 instead of 155).
 // ---------------------------------------------------------------------------
-constexpr int kUStage = 16;  // staged elements per LDS flush (>= twojmax + 1)
+#ifndef SNAP_U_STAGE
+#define SNAP_U_STAGE 16
+#endif
+#ifndef SNAP_U_WAVES_PER_EU
+#define SNAP_U_WAVES_PER_EU 2
+#endif
+constexpr int kUStage = SNAP_U_STAGE;  // staged elements per LDS flush (>= twojmax + 1)
 constexpr int kUAtoms = 4;   // atoms per wavefront
 constexpr int kUSlots = 16;  // lanes per atom
 constexpr int kUChunk = 2 * kUSlots;  // pairs per atom per chunk
@@ -295,7 +301,7 @@ __device__ __forceinline__ void slot_geometry(bool valid, int i, int t, bool fir
 }
 
 template <int TJ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_compute_u(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SNAP_U_WAVES_PER_EU, 8))) void k_compute_u(
     int n, int npad, const double *__restrict__ pos, const int *__restrict__ off,
     const int *__restrict__ nbr, Geom g, const UInfo *__restrict__ uinfo, double2 *__restrict__ U,
     int *__restrict__ pair_atom, int *__restrict__ flag)

@@ -17,10 +17,12 @@ __device__ __forceinline__ int fbase_rt(int J)
     return (J * (J + 1) * (2 * J + 1)) / 6;  // sum_{k=1}^{J} k^2
 }
 // Full row px of U^Jx (true values), elements f = fbase(Jx) + px (Jx+1) + q:
-// one buffer descriptor for the row (scalar registers), the element offset
-// in the scalar offset, the atom in the lane offset.  Entries q > Jx, and
-// the whole row when it is not valid, are zero, so that products with them
-// vanish.
+// one buffer descriptor for the row (scalar registers) whose size is the
+// row's Jx + 1 elements of npad atoms (none when the row is not valid), and
+// the element and atom in the lane offset.  The descriptor's range check
+// (on the lane offset) returns zero for the entries q > Jx and for a row
+// that is not valid, so that products with them vanish: no per-entry test,
+// branch or zeroing.
 template <int TJ>
 __device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int px, bool valid,
                                               const double2 *__restrict__ U, int npad,
@@ -29,16 +31,14 @@ __device__ __forceinline__ void load_full_row(double2 (&r)[TJ + 1], int Jx, int 
     const int pv = valid ? px : 0;
     const double2 *base = U + (size_t)(fbase_rt(Jx) + pv * (Jx + 1)) * (size_t)npad;
     __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)base, (short)0, (Jx + 1) * npad * 16, 0x00020000);
+        (void *)base, (short)0, valid ? (Jx + 1) * npad * 16 : 0, 0x00020000);
 #pragma unroll
     for (int q = 0; q <= TJ; ++q) {
-        r[q] = make_double2(0.0, 0.0);
-        if (valid && q <= Jx) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, q * npad * 16, 0);
-            r[q] = make_double2(
-                __builtin_bit_cast(double, (unsigned long long)v[0] | ((unsigned long long)v[1] << 32)),
-                __builtin_bit_cast(double, (unsigned long long)v[2] | ((unsigned long long)v[3] << 32)));
-        }
+        const auto v =
+            __builtin_amdgcn_raw_buffer_load_b128(rs, voff + (unsigned)(q * npad * 16), 0, 0);
+        r[q] = make_double2(
+            __builtin_bit_cast(double, (unsigned long long)v[0] | ((unsigned long long)v[1] << 32)),
+            __builtin_bit_cast(double, (unsigned long long)v[2] | ((unsigned long long)v[3] << 32)));
     }
 }
 
