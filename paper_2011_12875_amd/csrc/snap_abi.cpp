@@ -343,7 +343,10 @@ static Geom make_geom(const snap_ctx *c, const double box[3])
     g.rmin0 = c->prm.rmin0;
     g.wself = c->prm.wself;
     g.switch_flag = c->prm.switch_flag;
-    for (int d = 0; d < 3; ++d) g.box[d] = box[d] > 0.0 ? box[d] : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        g.box[d] = box[d] > 0.0 ? box[d] : 0.0;
+        g.ibox[d] = box[d] > 0.0 ? 1.0 / box[d] : 0.0;
+    }
     return g;
 }
 

@@ -91,24 +91,26 @@ __device__ __forceinline__ bool pair_geometry(const double rv[3], const Geom &g,
     const bool ok = (r >= 1e-10) && (r < 1e300);  // false for NaN too
     const double rs = ok ? r : 1.0;
     pg.r = rs;
-    pg.n[0] = ok ? rv[0] / rs : 0.0;
-    pg.n[1] = ok ? rv[1] / rs : 0.0;
-    pg.n[2] = ok ? rv[2] / rs : 1.0;
-    const double span = rc - g.rmin0;
-    const double th0 = g.rfac0 * M_PI * (rs - g.rmin0) / span;
+    // two divisions per pair (1/r, 1/(rc - rmin0)); the rest are products
+    const double ir = 1.0 / rs;
+    pg.n[0] = ok ? rv[0] * ir : 0.0;
+    pg.n[1] = ok ? rv[1] * ir : 0.0;
+    pg.n[2] = ok ? rv[2] * ir : 1.0;
+    const double ispan = 1.0 / (rc - g.rmin0);
+    const double x = (rs - g.rmin0) * ispan;  // 0 at rmin0, 1 at the cutoff
     double s0, c0;
-    sincos(th0, &s0, &c0);
+    sincos(g.rfac0 * M_PI * x, &s0, &c0);
     pg.c0 = c0;
     pg.s0 = s0;
-    pg.dth0 = g.rfac0 * M_PI / span;
+    pg.dth0 = g.rfac0 * M_PI * ispan;
     pg.a = ok ? make_double2(c0, -s0 * pg.n[2]) : make_double2(1.0, 0.0);
     pg.b = ok ? make_double2(s0 * pg.n[1], -s0 * pg.n[0]) : make_double2(0.0, 0.0);
     double fc = 1.0, dfdr = 0.0;
     if (g.switch_flag && rs > g.rmin0) {
         double sx, cx;
-        sincos(M_PI * (rs - g.rmin0) / span, &sx, &cx);
+        sincos(M_PI * x, &sx, &cx);
         fc = 0.5 * (cx + 1.0);
-        dfdr = -0.5 * M_PI / span * sx;
+        dfdr = -0.5 * M_PI * ispan * sx;
     }
     const bool inside = ok && r < rc;
     pg.fc = inside ? w * fc : 0.0;
@@ -122,7 +124,7 @@ __device__ __forceinline__ void min_image(const double *__restrict__ pos, int i,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double x = pos[3 * k + d] - pos[3 * i + d];
-        if (g.box[d] > 0.0) x -= g.box[d] * rint(x / g.box[d]);
+        if (g.box[d] > 0.0) x -= g.box[d] * rint(x * g.ibox[d]);
         rv[d] = x;
     }
 }

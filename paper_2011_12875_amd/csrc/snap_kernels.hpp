@@ -10,6 +10,7 @@ namespace snapmi {
 struct Geom {
     double rcut, rfac0, rmin0, wself;
     double box[3];
+    double ibox[3];  // 1 / box (0 on open axes)
     int switch_flag;
     // several elements (type == nullptr: one element, cutoff rcut, unit
     // weights): the pair (i, k) has the cutoff rcutfac (erad[t_i] + erad[t_k])

@@ -26,23 +26,55 @@ using namespace dev;
 // for 70 extra elements per pair at 2J = 8 (225 instead of 155).
 // ---------------------------------------------------------------------------
 #ifndef SNAP_U_STAGE
-#define SNAP_U_STAGE 16
+#define SNAP_U_STAGE 12
 #endif
 #ifndef SNAP_U_WAVES_PER_EU
-#define SNAP_U_WAVES_PER_EU 2
+#define SNAP_U_WAVES_PER_EU 3
 #endif
-constexpr int kUStage = SNAP_U_STAGE;  // staged elements per LDS flush (>= twojmax + 1)
+// staged elements per LDS flush (at least a level, 2J_max + 1): twelve keep a
+// workgroup's LDS under 13.3 KB, so that three wavefronts fit per SIMD
+constexpr int ustage(int TJ) { return TJ + 1 > SNAP_U_STAGE ? TJ + 1 : SNAP_U_STAGE; }
 constexpr int kUAtoms = 4;   // atoms per wavefront
 constexpr int kUSlots = 16;  // lanes per atom
 constexpr int kUChunk = 2 * kUSlots;  // pairs per atom per chunk
 
-// LDS of one workgroup: staged values of the four atoms' lanes, the element
-// of each staged slot, and the element table (full-matrix index, mirror
-// index, normalisation, mirror sign).
+// Destination of the k-th element a workgroup emits: full-matrix index
+// (bits 0-23), diagonal flag (bit 24), mirror sign negative (bit 25); mirror
+// index (-1: none); normalisation N.  Written once per workgroup, so that a
+// flush reads it from LDS instead of a table in global memory.
+struct USlot {
+    int code, fm;
+    double nrm;
+};
+
+// Workgroups per group of atoms.  Up to 2J = 4 one walks every column in
+// turn: the pair geometry (square root, two sine-cosine pairs, divisions)
+// then costs more than the short columns, and the split would compute it
+// once per column.  Above, one workgroup per column: with its seed path each
+// costs about the same ((2J_max+1)(2J_max+2)/2 elements, 45 at 2J = 8).
+template <int TJ>
+constexpr int kUGroups = (TJ <= 4) ? 1 : TJ / 2 + 1;
+
+// Elements emitted before level J of column Q (counting, when one workgroup
+// walks every column, the columns before Q too).
+constexpr int emit_index(int TJ, int Q, int J)
+{
+    int k = 0;
+    if (TJ <= 4)
+        for (int q = 0; q < Q; ++q)
+            for (int j = (q ? 2 * q : 0); j <= TJ; ++j) k += j + 1;
+    for (int j = (Q ? 2 * Q : 0); j < J; ++j) k += j + 1;
+    return k;
+}
+// most elements one workgroup emits (column 0, or every column)
+constexpr int emit_max(int TJ) { return TJ <= 4 ? emit_index(TJ, TJ / 2 + 1, 0) : emit_index(TJ, 0, TJ + 1); }
+
+// LDS of one workgroup: staged values of the four atoms' lanes and the
+// destinations of every element it emits.
+template <int TJ, int NS>
 struct UStage {
-    double2 v[kUStage][65];
-    int code[kUStage];
-    const UInfo *table;
+    double2 v[NS][65];
+    USlot slot[emit_max(TJ)];
 };
 
 // The emission order of column Q is static: levels J = (Q ? 2Q : 0)..TJ,
@@ -58,7 +90,7 @@ constexpr StagePos stage_pos(int TJ, int Q, int J)
     int nst = 0;
     for (int j = (Q ? 2 * Q : 0); j <= TJ; ++j) {
         int fl = 0;
-        if (nst + j + 1 > kUStage) {
+        if (nst + j + 1 > ustage(TJ)) {
             fl = nst;
             nst = 0;
         }
@@ -77,45 +109,86 @@ constexpr int stage_end(int TJ, int Q)
 // them to U, stored as full matrices of true values: U(p, q) = N * sum and
 // its mirror U(J-p, J-q) = (-1)^(p-q) conj(U(p, q)).  The first chunk of
 // neighbours starts from w_self on the diagonal (where N = 1).
-template <int NST>
-__device__ __forceinline__ void u_flush(UStage &st, int lane, int i0, int n, int npad, int chunk,
-                                        double wself, double2 *__restrict__ U)
+template <int TJ, int NS, int NST, int BASE>
+__device__ __forceinline__ void u_flush(UStage<TJ, NS> &st, int lane, int i0, int n, int npad,
+                                        int chunk, double wself, double2 *__restrict__ U)
 {
+    static_assert(NS <= 16 && kUAtoms * 16 == 64, "one (atom, slot) per lane");
     __syncthreads();
+    // lane = (atom hh, slot ss) whatever NST is: the per-lane addresses are
+    // the same for every flush (computed once, not once per flush size)
+    const int hh = lane >> 4, ss = lane & 15;
+    if (ss < NST) {
+        const USlot ui = st.slot[BASE + ss];
+        double sr = 0.0, si = 0.0;
 #pragma unroll
-    for (int k0 = 0; k0 < kUAtoms * NST; k0 += 64) {
-        const int k = k0 + lane;
-        if (k < kUAtoms * NST) {
-            const int hh = k / NST;
-            const int ss = k - hh * NST;
-            const int code = st.code[ss];
-            const UInfo ui = st.table[code & 0xffffff];
-            double sr = 0.0, si = 0.0;
+        for (int j0 = 0; j0 < kUSlots; j0 += 4) {
+            // four reads in flight at a time: all sixteen hoisted would hold
+            // 64 registers on top of the recursion state
 #pragma unroll
-            for (int j = 0; j < kUSlots; ++j) {
+            for (int j = j0; j < j0 + 4; ++j) {
                 const double2 v = st.v[ss][hh * kUSlots + j];
                 sr += v.x;
                 si += v.y;
             }
-            const int ia = i0 + hh;
-            if (ia < n) {
-                const size_t idx = (size_t)ui.fi * npad + ia;
-                double br = 0.0, bi = 0.0;
-                if (chunk == 0) {
-                    br = (code >> 24) ? wself : 0.0;
-                } else {
-                    const double2 old = U[idx];
-                    br = old.x;
-                    bi = old.y;
-                }
-                const double2 v = make_double2(br + ui.nrm * sr, bi + ui.nrm * si);
-                U[idx] = v;
-                if (ui.fm >= 0)
-                    U[(size_t)ui.fm * npad + ia] = make_double2(ui.msign * v.x, -ui.msign * v.y);
+            pin(sr);
+            pin(si);
+            memory_fence_compiler();
+        }
+        const int ia = i0 + hh;
+        if (ia < n) {
+            const size_t idx = (size_t)(ui.code & 0xffffff) * npad + ia;
+            double br = 0.0, bi = 0.0;
+            if (chunk == 0) {
+                br = ((ui.code >> 24) & 1) ? wself : 0.0;
+            } else {
+                const double2 old = U[idx];
+                br = old.x;
+                bi = old.y;
+            }
+            const double2 v = make_double2(br + ui.nrm * sr, bi + ui.nrm * si);
+            U[idx] = v;
+            if (ui.fm >= 0) {
+                const double ms = (ui.code >> 25) ? -1.0 : 1.0;
+                U[(size_t)ui.fm * npad + ia] = make_double2(ms * v.x, -ms * v.y);
             }
         }
     }
     __syncthreads();
+}
+
+// Fill the slot table: lane k takes the k-th element the workgroup of column
+// colq emits (levels from 2 colq up, rows 0..J of each; every column in turn
+// up to 2J = 4) and copies its destination from the element table.
+template <int TJ, int NS>
+__device__ __forceinline__ void u_init_slots(UStage<TJ, NS> &st, int lane, int colq,
+                                             const UInfo *__restrict__ uinfo)
+{
+    const int q0 = kUGroups<TJ> == 1 ? 0 : colq;
+    const int q1 = kUGroups<TJ> == 1 ? TJ / 2 : colq;
+    for (int k = lane; k < emit_max(TJ); k += 64) {
+        int rem = k, Q = q0, J = q0 ? 2 * q0 : 0;
+        bool ok = true;
+        while (rem > J) {
+            rem -= J + 1;
+            if (++J > TJ) {
+                if (++Q > q1) {
+                    ok = false;
+                    break;
+                }
+                J = 2 * Q;
+            }
+        }
+        if (!ok) break;
+        int hb = 0;  // first half index of rank J
+        for (int j = 0; j < J; ++j) hb += (j + 1) * (j / 2 + 1);
+        const UInfo ui = uinfo[hb + Q * (J + 1) + rem];
+        USlot sl;
+        sl.code = ui.fi | ((rem == Q) ? (1 << 24) : 0) | ((ui.msign < 0.0) ? (1 << 25) : 0);
+        sl.fm = ui.fm;
+        sl.nrm = ui.nrm;
+        st.slot[k] = sl;
+    }
 }
 
 // the two pairs a lane walks: geometry and recursion state
@@ -140,17 +213,17 @@ __device__ __forceinline__ void step2(int J, UPair2<TJ> &w)
 }
 
 template <int TJ, int Q, int J>
-__device__ __forceinline__ void u_emit(UStage &st, int lane, const UPair2<TJ> &w, int i0, int n,
+__device__ __forceinline__ void u_emit(UStage<TJ, ustage(TJ)> &st, int lane, const UPair2<TJ> &w, int i0, int n,
                                        int npad, int chunk, double wself, double2 *__restrict__ U)
 {
     constexpr StagePos sp = stage_pos(TJ, Q, J);
-    if constexpr (sp.flushed > 0) u_flush<sp.flushed>(st, lane, i0, n, npad, chunk, wself, U);
-    constexpr int ebase = hbase_of(J) + Q * (J + 1);
+    if constexpr (sp.flushed > 0)
+        u_flush<TJ, ustage(TJ), sp.flushed, emit_index(TJ, Q, J) - sp.flushed>(st, lane, i0, n, npad,
+                                                                              chunk, wself, U);
 #pragma unroll
     for (int p = 0; p <= J; ++p) {
         // the two pairs' f_c u, summed
         st.v[sp.slot + p][lane] = make_double2(w.c0[p].x + w.c1[p].x, w.c0[p].y + w.c1[p].y);
-        if (lane == 0) st.code[sp.slot + p] = (ebase + p) | ((p == Q) ? (1 << 24) : 0);
     }
 }
 
@@ -158,7 +231,7 @@ __device__ __forceinline__ void u_emit(UStage &st, int lane, const UPair2<TJ> &w
 // level 2Q+1 is also mirrored into the seed of column Q+1.
 template <int TJ, int Q, int J, bool SEED>
 struct ULevels {
-    __device__ __forceinline__ static void run(UStage &st, int lane, UPair2<TJ> &w, int i0, int n,
+    __device__ __forceinline__ static void run(UStage<TJ, ustage(TJ)> &st, int lane, UPair2<TJ> &w, int i0, int n,
                                                int npad, int chunk, double wself,
                                                double2 *__restrict__ U)
     {
@@ -179,7 +252,7 @@ struct ULevels {
 };
 template <int TJ, int Q, bool SEED>
 struct ULevels<TJ, Q, TJ + 1, SEED> {
-    __device__ __forceinline__ static void run(UStage &, int, UPair2<TJ> &, int, int, int, int,
+    __device__ __forceinline__ static void run(UStage<TJ, ustage(TJ)> &, int, UPair2<TJ> &, int, int, int, int,
                                                double, double2 *__restrict__)
     {
     }
@@ -201,6 +274,62 @@ __device__ __forceinline__ void start_column(UPair2<TJ> &w, double fc0, double f
         w.c1[0] = make_double2(fc1, 0.0);
     }
 }
+
+// Start column q of both pairs in place: the seed of column q is already in
+// the first 2q rows (mirrored there by the previous column's walk); the rows
+// above it start at zero.  Column 0 starts from f_c.
+template <int TJ, int q>
+__device__ __forceinline__ void start_column_inplace(UPair2<TJ> &w, double fc0, double fc1)
+{
+#pragma unroll
+    for (int p = 0; p <= TJ; ++p)
+        if (q == 0 || p >= 2 * q) {
+            w.c0[p] = make_double2(0.0, 0.0);
+            w.c1[p] = make_double2(0.0, 0.0);
+        }
+    if constexpr (q == 0) {
+        w.c0[0] = make_double2(fc0, 0.0);
+        w.c1[0] = make_double2(fc1, 0.0);
+    }
+}
+
+// Column q at level 2q+1 -> seed of column q+1, in place:
+//   poly_{p, q+1} = (-1)^(q+1-p) conj(poly_{2q+1-p, q}),  p = 0..2q+1
+template <int TJ, int Q>
+__device__ __forceinline__ void mirror_inplace(double2 (&col)[TJ + 1])
+{
+#pragma unroll
+    for (int p = 0; p < Q + 1; ++p) {
+        const int m = 2 * Q + 1 - p;  // > p
+        const double sp = ((Q + 1 - p) & 1) ? -1.0 : 1.0;
+        const double sm = ((Q + 1 - m) & 1) ? -1.0 : 1.0;
+        const double2 x = col[p], y = col[m];
+        col[p] = make_double2(sp * y.x, -sp * y.y);
+        col[m] = make_double2(sm * x.x, -sm * x.y);
+    }
+}
+
+// Seed path of a single-column workgroup, in place: columns q = 0..Q-1 to
+// level 2q+1, each mirrored into the start of the next.  Nothing is emitted.
+template <int TJ, int q, int Q>
+struct USeedInPlace {
+    __device__ __forceinline__ static void run(UPair2<TJ> &w, double fc0, double fc1)
+    {
+        if constexpr (q < Q) {
+            start_column_inplace<TJ, q>(w, fc0, fc1);
+#pragma unroll
+            for (int J = (q == 0 ? 1 : 2 * q); J <= 2 * q + 1; ++J) step2<TJ>(J, w);
+            mirror_inplace<TJ, q>(w.c0);
+            mirror_inplace<TJ, q>(w.c1);
+#pragma unroll
+            for (int p = 0; p <= 2 * q + 1; ++p) {
+                pin(w.c0[p]);
+                pin(w.c1[p]);
+            }
+            USeedInPlace<TJ, q + 1, Q>::run(w, fc0, fc1);
+        }
+    }
+};
 
 // Seed path: column q from its seed, levels up to 2q+1, mirrored into the
 // seed of column q+1; for q = 0 .. Q-1.  Nothing is emitted.
@@ -227,42 +356,42 @@ struct USeedPath {
 // Columns Q..TJ/2 walked one after another, each from the seed the previous
 // walk left (CHAIN), or column Q alone (its seed path first when Q > 0).
 template <int TJ, int Q, bool CHAIN>
-__device__ __forceinline__ void u_walk(UStage &st, int lane, UPair2<TJ> &w, double fc0, double fc1,
+__device__ __forceinline__ void u_walk(UStage<TJ, ustage(TJ)> &st, int lane, UPair2<TJ> &w, double fc0, double fc1,
                                        int i0, int n, int npad, int chunk, double wself,
                                        double2 *__restrict__ U)
 {
     constexpr bool NEXT = CHAIN && Q < TJ / 2;
-    start_column<TJ, Q>(w, fc0, fc1);
+    if constexpr (CHAIN)
+        start_column<TJ, Q>(w, fc0, fc1);
+    else
+        start_column_inplace<TJ, Q>(w, fc0, fc1);
     if constexpr (Q == 0) u_emit<TJ, 0, 0>(st, lane, w, i0, n, npad, chunk, wself, U);
     ULevels<TJ, Q, (Q == 0 ? 1 : 2 * Q), NEXT>::run(st, lane, w, i0, n, npad, chunk, wself, U);
-    u_flush<stage_end(TJ, Q)>(st, lane, i0, n, npad, chunk, wself, U);
+    u_flush<TJ, ustage(TJ), stage_end(TJ, Q), emit_index(TJ, Q, TJ + 1) - stage_end(TJ, Q)>(
+        st, lane, i0, n, npad, chunk, wself, U);
     if constexpr (NEXT) u_walk<TJ, Q + 1, true>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
 }
 
 // Workgroup column Q of one chunk of pairs: the seed path, then the walk.
 template <int TJ, int Q, bool CHAIN>
-__device__ __forceinline__ void u_column(UStage &st, int lane, UPair2<TJ> &w, double fc0,
+__device__ __forceinline__ void u_column(UStage<TJ, ustage(TJ)> &st, int lane, UPair2<TJ> &w, double fc0,
                                          double fc1, int i0, int n, int npad, int chunk,
                                          double wself, double2 *__restrict__ U)
 {
+    if constexpr (CHAIN) {
 #pragma unroll
-    for (int p = 0; p <= TJ; ++p) w.s0[p] = w.s1[p] = make_double2(0.0, 0.0);
-    USeedPath<TJ, 0, Q>::run(w, fc0, fc1);
+        for (int p = 0; p <= TJ; ++p) w.s0[p] = w.s1[p] = make_double2(0.0, 0.0);
+        USeedPath<TJ, 0, Q>::run(w, fc0, fc1);
+    } else {
+        USeedInPlace<TJ, 0, Q>::run(w, fc0, fc1);
+    }
     u_walk<TJ, Q, CHAIN>(st, lane, w, fc0, fc1, i0, n, npad, chunk, wself, U);
 }
-
-// Workgroups per group of atoms.  Up to 2J = 4 one walks every column in
-// turn: the pair geometry (square root, two sine-cosine pairs, divisions)
-// then costs more than the short columns, and the split would compute it
-// once per column.  Above, one workgroup per column: with its seed path each
-// costs about the same ((2J_max+1)(2J_max+2)/2 elements, 45 at 2J = 8).
-template <int TJ>
-constexpr int kUGroups = (TJ <= 4) ? 1 : TJ / 2 + 1;
 
 // uniform workgroup column index -> compile-time instance
 template <int TJ, int Q>
 struct UColumn {
-    __device__ __forceinline__ static void run(int col, UStage &st, int lane, UPair2<TJ> &w,
+    __device__ __forceinline__ static void run(int col, UStage<TJ, ustage(TJ)> &st, int lane, UPair2<TJ> &w,
                                                double fc0, double fc1, int i0, int n, int npad,
                                                int chunk, double wself, double2 *__restrict__ U)
     {
@@ -301,16 +430,16 @@ __device__ __forceinline__ void slot_geometry(bool valid, int i, int t, bool fir
 }
 
 template <int TJ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(SNAP_U_WAVES_PER_EU, 8))) void k_compute_u(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TJ <= 8 ? SNAP_U_WAVES_PER_EU : 2, 8))) void k_compute_u(
     int n, int npad, const double *__restrict__ pos, const int *__restrict__ off,
     const int *__restrict__ nbr, Geom g, const UInfo *__restrict__ uinfo, double2 *__restrict__ U,
     int *__restrict__ pair_atom, int *__restrict__ flag)
 {
-    __shared__ UStage st;
+    __shared__ UStage<TJ, ustage(TJ)> st;
     constexpr int NCOL = kUGroups<TJ>;
     const int lane = threadIdx.x;
     const int colq = (int)blockIdx.x % NCOL;  // uniform
-    if (lane == 0) st.table = uinfo;  // read after the first flush's barrier
+    u_init_slots<TJ>(st, lane, colq, uinfo);  // read after the first flush's barrier
     const int h = lane / kUSlots, slot = lane % kUSlots;
     const int i0 = ((int)blockIdx.x / NCOL) * kUAtoms;
     const int i = i0 + h;

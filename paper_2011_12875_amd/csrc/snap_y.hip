@@ -114,11 +114,15 @@ __device__ __forceinline__ void y_contrib(int J1, int J2, int p1lo, int p1hi, in
         int j1 = J1, j2 = J2, qn = nq;
         asm volatile("" : "+s"(j1), "+s"(j2), "+s"(qn));
         const double *cp = cpt + cp_off + 2 * (p1 - p1lo);
+        // the row coefficients are wavefront-uniform; at the two ends of the
+        // union range one of the rows has none (zero), and its product is
+        // skipped by a scalar branch
+        const double c0 = cp[0], c1 = cp[1];
         load_full_row<TJ>(s1, j1, p1, true, U, npad, voff);
-        if (kTwo && two) row_product<TJ, D>(s1, s2, cq, f * cp[1], qn, acc1);
+        if (kTwo && two && c1 != 0.0) row_product<TJ, D>(s1, s2, cq, f * c1, qn, acc1);
         const int p2 = p - p1 + D;
         load_full_row<TJ>(s2, j2, p2, p2 >= 0, U, npad, voff);
-        row_product<TJ, D>(s1, s2, cq, f * cp[0], qn, acc0);
+        if (c0 != 0.0) row_product<TJ, D>(s1, s2, cq, f * c0, qn, acc0);
     }
     // ysum[(r (J_max/2 + 1) + q) 64 + lane]: this lane's entries only
 #pragma unroll
