@@ -81,7 +81,8 @@ typedef struct {
                         * one wavefront per block of pairs                   */
     int dedr_waves;    /* generator form: wavefronts that split the columns
                         * of a block of 64 pairs, 1 .. 4 (0: auto, 1 up to
-                        * 2J = 4, else 2)                                    */
+                        * 2J = 4, else 2; 3 at 2J = 7 and 8 when the pair
+                        * blocks number at most four per compute unit)      */
     int u_kernel;      /* compute_U variant: 0 auto (1), 1 one workgroup per
                         * column of the stored half (two pairs per lane, seed
                         * paths), 2 one pair per lane walking every column,

@@ -496,7 +496,14 @@ hipError_t launch_gen_t(int mapping, int waves, int ncu, int npairs, int nh, con
     const int ppb = pairs_per_block(npairs, ncu);
     const int nblk = (npairs + ppb - 1) / ppb;
     const int ngrid = ((nblk + 7) / 8) * 8;
-    const int nr = waves > 0 ? waves : kGenRoles<TJ>;
+    int nr = waves > 0 ? waves : kGenRoles<TJ>;
+    // At 2J = 7 and 8 the two-way column split is uneven (at 2J = 8 the
+    // larger share is 430 against 358 elements of the cost model) and a
+    // three-way split shortens the longest share; it pays while the blocks
+    // leave room for a third wavefront per SIMD (at most four blocks per CU):
+    // 2000 atoms, 2J = 8: 19.2 -> 16.5 us, 2J = 7: 15.8 -> 15.2 us, measured.
+    // With more blocks the extra seed paths cost more than they save.
+    if (waves == 0 && (TJ == 7 || TJ == 8) && ncu > 0 && nblk <= 4 * ncu) nr = 3;
     if (mapping == 1) {
         launch_gen_nr<TJ, false, kGenRoles<TJ>>(ngrid, s, npairs, ppb, nh, pos, nbr, pair_atom, Y,
                                                 g, dE);
