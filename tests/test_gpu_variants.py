@@ -1,5 +1,6 @@
 """GPU parity of the selectable kernel variants (snap_params.y_kernel,
-snap_params.dedr_dirs) against the CPU oracle, on every atom and pair.
+dedr_dirs, dedr_kernel, dedr_waves, u_kernel) against the CPU oracle, on
+every atom and pair.
 
 Tolerances as in test_gpu_parity: energies within 1e-11 relative to
 max(|E_i|, mean |E_i|), forces and pair derivatives within 1e-10 eV/A.
@@ -82,6 +83,24 @@ def test_dedr_generator_every_twojmax(tj, kern):
     beta = wl.beta(wl.ncoeff(tj), 70 + tj)
     print("case twojmax", tj, "dedr_kernel", kern, flush=True)
     _compare(pos, box, beta, tj, dedr_kernel=kern)
+
+
+@pytest.mark.parametrize("waves", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("tj", [7, 8])
+def test_dedr_waves_every_split(tj, waves):
+    """The generator form with its columns split over 1 .. 4 wavefronts, and
+    the automatic choice (0: three at 2J = 7 and 8 on a system this small)."""
+    pos, box = wl.bcc(3, 0.1, 110 + tj)
+    beta = wl.beta(wl.ncoeff(tj), 120 + tj)
+    print("case twojmax", tj, "dedr_waves", waves, flush=True)
+    _compare(pos, box, beta, tj, dedr_waves=waves)
+
+
+@pytest.mark.parametrize("waves", [2, 3])
+def test_dedr_waves_2000_atoms(waves):
+    pos, box, beta, tj = wl.make("bcc2000_2j8")
+    print("case bcc2000_2j8 dedr_waves", waves, flush=True)
+    _compare(pos, box, beta, tj, dedr_waves=waves)
 
 
 @pytest.mark.parametrize("kern", [1, 2, 3])
