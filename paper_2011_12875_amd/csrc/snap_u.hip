@@ -438,10 +438,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TJ <= 8 ? SN
     __shared__ UStage<TJ, ustage(TJ)> st;
     constexpr int NCOL = kUGroups<TJ>;
     const int lane = threadIdx.x;
-    const int colq = (int)blockIdx.x % NCOL;  // uniform
+    // Workgroup w runs on XCD w mod 8 and computes the atom groups of the
+    // 64-atom blocks congruent to it mod 8, block by block, all columns of a
+    // group on the same XCD: the partial lines of U that the column
+    // workgroups of an atom group write meet in one L2, which is also the L2
+    // of the XCD whose compute_Y workgroups read that block.
+    constexpr int GPB = 64 / kUAtoms;
+    const int wg = (int)blockIdx.x;
+    const int kk = wg >> 3;
+    const int kb = kk / (GPB * NCOL), rem = kk - kb * (GPB * NCOL);
+    const int colq = rem % NCOL;  // uniform
+    const int i0 = (((wg & 7) + 8 * kb) * GPB + rem / NCOL) * kUAtoms;
     u_init_slots<TJ>(st, lane, colq, uinfo);  // read after the first flush's barrier
     const int h = lane / kUSlots, slot = lane % kUSlots;
-    const int i0 = ((int)blockIdx.x / NCOL) * kUAtoms;
     const int i = i0 + h;
     int mx = 0;
 #pragma unroll
@@ -732,7 +741,9 @@ hipError_t launch_u_t(int variant, int n, int npad, const double *pos, const int
                            uinfo, U, pair_atom, flag);
         return hipGetLastError();
     }
-    const int nblk = ((n + kUAtoms - 1) / kUAtoms) * kUGroups<TJ>;
+    // 64-atom blocks padded to a multiple of 8 (the groups past n walk empty
+    // pairs and write nothing)
+    const int nblk = ((n + 64 * 8 - 1) / (64 * 8)) * 8 * (64 / kUAtoms) * kUGroups<TJ>;
     hipLaunchKernelGGL(k_compute_u<TJ>, dim3(nblk), dim3(64), 0, s, n, npad, pos, off, nbr, g,
                        uinfo, U, pair_atom, flag);
     return hipGetLastError();
