@@ -124,7 +124,12 @@ __global__ __launch_bounds__(256) void k_gather(int n, int npad, int nrows,
                                                 double *__restrict__ force)
 {
     constexpr int L = kGatherLanes;
-    const int g = blockIdx.x * (256 / L) + (threadIdx.x / L);
+    // workgroup w runs on XCD w mod 8 and takes atoms of the 64-atom blocks
+    // congruent to it mod 8, whose energy shares that XCD's compute_Y wrote
+    constexpr int WPB = 64 / (256 / L);  // workgroups per 64-atom block
+    const int wq = (int)blockIdx.x >> 3;
+    const int blk = 8 * (wq / WPB) + ((int)blockIdx.x & 7);
+    const int g = blk * 64 + (wq % WPB) * (256 / L) + (threadIdx.x / L);
     const int s = threadIdx.x % L;
     const int i = g < n ? g : n - 1;
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
@@ -322,8 +327,10 @@ hipError_t launch_gather(int n, int npad, int nrows, const int *off, const int *
                          hipStream_t s)
 {
     constexpr int apb = 256 / kGatherLanes;  // atoms per block
-    hipLaunchKernelGGL(k_gather, dim3((n + apb - 1) / apb), dim3(256), 0, s, n, npad, nrows, off,
-                       rev, dE, Epart, energy, force);
+    // 64-atom blocks padded to a multiple of 8 (atoms past n write nothing)
+    const int ngrid = ((n + 64 * 8 - 1) / (64 * 8)) * 8 * (64 / apb);
+    hipLaunchKernelGGL(k_gather, dim3(ngrid), dim3(256), 0, s, n, npad, nrows, off, rev, dE, Epart,
+                       energy, force);
     return hipGetLastError();
 }
 
