@@ -280,18 +280,29 @@ __device__ __forceinline__ void gen_sums(const PairGeom &pg, const YS &ys, GenSt
     if constexpr (TJ >= 1 && CB < CE) gen_columns<TJ, 0, CB, CE>(st, pg.a, pg.b, ys);
 }
 
+// More columns [CB, CE) for a wavefront that already walked others: their
+// seed path from column 0, then their walk, added to the same sums.
+template <int TJ, int CB, int CE, class YS>
+__device__ __forceinline__ void gen_sums_more(const PairGeom &pg, const YS &ys, GenState<TJ> &st)
+{
+#pragma unroll
+    for (int p = 0; p <= TJ; ++p) st.seed[p] = make_double2(0.0, 0.0);
+    if constexpr (CB < CE) gen_columns<TJ, 0, CB, CE>(st, pg.a, pg.b, ys);
+}
+
 // dE for the three directions from the sums.
 template <int TJ>
 __device__ __forceinline__ void gen_finish(const PairGeom &pg, bool ok, const GenState<TJ> &st,
                                            double dE[3])
 {
     const double2 a = pg.a, b = pg.b;
+    const double ir = 1.0 / pg.r;  // one division instead of nine
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
         const double nal = pg.n[al];
-        const double dnx = ((al == 0 ? 1.0 : 0.0) - nal * pg.n[0]) / pg.r;
-        const double dny = ((al == 1 ? 1.0 : 0.0) - nal * pg.n[1]) / pg.r;
-        const double dnz = ((al == 2 ? 1.0 : 0.0) - nal * pg.n[2]) / pg.r;
+        const double dnx = ((al == 0 ? 1.0 : 0.0) - nal * pg.n[0]) * ir;
+        const double dny = ((al == 1 ? 1.0 : 0.0) - nal * pg.n[1]) * ir;
+        const double dnz = ((al == 2 ? 1.0 : 0.0) - nal * pg.n[2]) * ir;
         const double dth = pg.dth0 * nal;
         const double2 da = make_double2(-pg.s0 * dth, -(pg.c0 * dth * pg.n[2] + pg.s0 * dnz));
         const double2 db = make_double2(pg.c0 * dth * pg.n[1] + pg.s0 * dny,
@@ -328,7 +339,17 @@ __device__ __forceinline__ void role_sums(int role, const PairGeom &pg, const YS
     if constexpr (R < NR) {
         if (role == R) {
             constexpr int b = kColB<TJ, NR, R>, e = kColB<TJ, NR, R + 1>;
-            if constexpr (b < e) {
+            if constexpr (TJ == 8 && NR == 3) {
+                // columns {0}, {1, 4}, {2, 3}: the longest share is 329
+                // elements of the cost model instead of 358 for the best
+                // contiguous split {0}, {1}, {2, 3, 4}
+                if constexpr (R == 0) gen_sums<TJ, 0, 1>(pg, ys, st);
+                if constexpr (R == 1) {
+                    gen_sums<TJ, 1, 2>(pg, ys, st);
+                    gen_sums_more<TJ, 4, 5>(pg, ys, st);
+                }
+                if constexpr (R == 2) gen_sums<TJ, 2, 4>(pg, ys, st);
+            } else if constexpr (b < e) {
                 gen_sums<TJ, b, e>(pg, ys, st);
             } else {
                 // no columns for this wavefront (more wavefronts than columns)
